@@ -1,0 +1,187 @@
+/*
+ * rqa.h -- C ABI of librqa: recurrence quantification analysis (RQA) of FP32
+ * time series on an MI355X (gfx950) GPU.
+ *
+ * Method (Rawald, Sips, Marwan, "PyRQA - Conducting Recurrence Quantification
+ * Analysis on Very Long Time Series Efficiently"):
+ *   Sect. 2   time-delay embedding, similarity of vector pairs under a norm,
+ *             fixed-radius neighbourhood -> binary recurrence matrix; diagonal,
+ *             vertical and white vertical lines; their frequency distributions
+ *             and the measures derived from them;
+ *   Sect. 4.2 the three operators (create the recurrence matrix, detect diagonal
+ *             lines, detect vertical lines) -- fused here into one pass over
+ *             tiles of the upper triangle; the N x N matrix is never stored;
+ *   Sect. 4.1 divide & recombine with carry-over of lines that cross tile
+ *             borders;
+ *   Sect. 7.2 the parameter set (embedding_dimension, time_delay,
+ *             similarity_measure, FixedRadius(radius), minimum diagonal,
+ *             vertical and white vertical line lengths);
+ *   Sect. 8.1 Tab. 3 the measure names (RR, DET, L, Lmax, DIV, L_entr, LAM, TT,
+ *             Vmax, V_entr).
+ *
+ * Conventions (identical in every entry point):
+ *  - n_points is the length of the scalar series; the number of delay vectors is
+ *    n = n_points - (m-1)*tau.
+ *  - Cell (i,j) is recurrent when the norm of x_i - x_j, accumulated in FP32 in
+ *    ascending coordinate order without fused multiply-add, is <= eps (for L2
+ *    the squared sum is compared with fl32(eps*eps)); cells with |i-j| < theiler
+ *    are forced to 0.  The matrix is symmetric.
+ *  - Histograms cover the whole n x n masked matrix (both triangles, runs that
+ *    touch the border included) and are indexed by line length: entry l counts
+ *    the lines of length l, entry 0 is always 0; length n+1 arrays.
+ *  - Device pointers are hipMalloc'd (or PyTorch CUDA tensor) memory on the
+ *    current HIP device; host pointers are ordinary host memory.
+ *  - Every function returns RQA_OK (0) or a negative RQA_E* code; nothing
+ *    aborts.  A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef RQA_H
+#define RQA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define RQA_OK 0
+#define RQA_EINVAL (-1)      /* an argument is out of range or a pointer is NULL   */
+#define RQA_ETOOSHORT (-2)   /* n_points gives fewer than one delay vector          */
+#define RQA_ENOMEM (-3)      /* device or host allocation failed                     */
+#define RQA_EDEVICE (-4)     /* a HIP runtime call or kernel launch failed           */
+#define RQA_ENONFINITE (-5)  /* the series holds NaN or +-Inf (detected on device)   */
+#define RQA_ESIZE (-6)       /* a caller buffer is shorter than required             */
+#define RQA_ESTATE (-7)      /* call order violated (e.g. result before run)         */
+#define RQA_EBUDGET (-8)     /* a job needs more device memory than the server owns  */
+#define RQA_EAGAIN (-9)      /* a served job is not finished yet                     */
+#define RQA_ENOTFOUND (-10)  /* unknown ticket                                       */
+
+/* Similarity measures (Sect. 7.2: L1, L2 and L-infinity norms). */
+#define RQA_NORM_L1 1
+#define RQA_NORM_L2 2
+#define RQA_NORM_LINF 3
+
+/* RQA parameters, the fields of PyRQA's Settings (Sect. 7.2) plus a Theiler
+ * window.  m >= 1, tau >= 1, eps finite and >= 0, norm in {1,2,3},
+ * lmin/vmin/wmin >= 1, theiler >= 0. */
+typedef struct rqa_params {
+    int32_t m;        /* embedding dimension                                 */
+    int32_t tau;      /* time delay                                          */
+    float eps;        /* fixed radius                                        */
+    int32_t norm;     /* RQA_NORM_*                                          */
+    int32_t lmin;     /* minimum diagonal line length                        */
+    int32_t vmin;     /* minimum vertical line length                        */
+    int32_t wmin;     /* minimum white vertical line length                  */
+    int32_t theiler;  /* cells with |i-j| < theiler are not recurrences      */
+} rqa_params;
+
+/* Measures in FP64, computed on the host from the integer histograms D (diag),
+ * V (vert), W (white).  N_rec = sum l*D(l); A = n^2 minus the Theiler band.
+ *   rr = N_rec/A; det = sum_{l>=lmin} l D / N_rec; l = sum_{l>=lmin} l D / sum_{l>=lmin} D;
+ *   lmax = max{l: D(l)>0}; div = 1/lmax; l_entr = -sum p ln p over l >= lmin;
+ *   lam = sum_{v>=vmin} v V / sum v V; tt = sum_{v>=vmin} v V / sum_{v>=vmin} V;
+ *   vmax, v_entr likewise; w = sum_{w>=wmin} w W / sum_{w>=wmin} W; wmax, w_entr.
+ * A ratio with a zero denominator is NaN. */
+typedef struct rqa_measures {
+    double rr, det, l, lmax, div, l_entr, lam, tt, vmax, v_entr, w, wmax, w_entr;
+    uint64_t n_rec;   /* number of recurrence points (both triangles)        */
+    int64_t n_vec;    /* number of delay vectors n                           */
+} rqa_measures;
+
+typedef struct rqa_handle rqa_handle;
+
+/* Create a computation for one parameter set (Sect. 7.3 RQAComputation.create).
+ * On success *out owns its device workspace (allocated lazily on the first run
+ * on the device that is current then).  RQA_EINVAL leaves *out untouched. */
+int rqa_create(rqa_handle **out, int32_t m, int32_t tau, float eps, int32_t norm,
+               int32_t lmin, int32_t vmin, int32_t wmin, int32_t theiler);
+
+/* Histogram length n+1 for a series of n_points under h's embedding.
+ * RQA_ETOOSHORT if n < 1. */
+int rqa_hist_len(const rqa_handle *h, int64_t n_points, int64_t *len);
+
+/* Enqueue the whole RQA of one device series on hip_stream (a hipStream_t;
+ * NULL = the null stream) and return without waiting (Sect. 7.4 run()).
+ * d_series: n_points contiguous FP32 values in device memory, owned by the
+ * caller, who keeps it alive and unmodified until rqa_result returns.
+ * Host-detectable errors return immediately; a non-finite series is flagged on
+ * the device and reported by rqa_result. */
+int rqa_run(rqa_handle *h, const float *d_series, int64_t n_points, void *hip_stream);
+
+/* Wait for the last rqa_run, copy its histograms into caller-owned HOST arrays
+ * of hist_len >= n+1 entries (any of diag/vert/white may be NULL) and fill *out
+ * (may be NULL).  RQA_ESTATE without a prior run, RQA_ESIZE if hist_len is too
+ * small, RQA_ENONFINITE if the series held NaN/Inf. */
+int rqa_result(rqa_handle *h, rqa_measures *out, uint64_t *diag, uint64_t *vert,
+               uint64_t *white, int64_t hist_len);
+
+/* Batched windowed RQA (many windows of uneven length over one device series,
+ * one persistent launch; the RQA X "epochs" idea of Sect. 3 run in parallel).
+ * offsets/lengths: count host int64 values, copied during the call; window w
+ * is d_series[offsets[w] .. offsets[w]+lengths[w]).  Every window uses h's
+ * parameters.  Asynchronous on hip_stream like rqa_run. */
+int rqa_run_batch(rqa_handle *h, const float *d_series, int64_t n_points,
+                  const int64_t *offsets, const int64_t *lengths, int32_t count,
+                  void *hip_stream);
+
+/* Results of window `index` of the last rqa_run_batch (waits for it). */
+int rqa_result_batch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag,
+                     uint64_t *vert, uint64_t *white, int64_t hist_len);
+
+/* Measures from host histograms of length n+1 (FP64, same definitions as
+ * rqa_result). */
+int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert,
+                           const uint64_t *white, int64_t n, const rqa_params *p,
+                           rqa_measures *out);
+
+/* Tile-shape override used by the autotuner and by shape-independence tests:
+ * waves per workgroup (1..16, rows per strip = 64*waves) and workgroups per
+ * launch (0 = one per compute unit).  Results never depend on these. */
+int rqa_set_tiling(rqa_handle *h, int32_t waves_per_group, int32_t groups);
+
+/* Release the handle and its device workspace (waits for outstanding work). */
+void rqa_destroy(rqa_handle *h);
+
+/* Static description of a return code. */
+const char *rqa_strerror(int code);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent jobs under a device-memory
+ * budget.  Jobs are admitted while their footprint fits, run on a pool of
+ * streams so that jobs submitted while others run overlap on the device, and
+ * are retired as they complete.  Thread-safe.
+ * ------------------------------------------------------------------------- */
+typedef struct rqa_server rqa_server;
+
+/* budget_bytes: device memory the server may hold for job workspaces;
+ * streams: concurrent launch slots (1..16). */
+int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams);
+
+/* Device bytes of the server pool a job of n_points occupies while it runs
+ * (histograms, flag and engine scratch; the series stays the caller's). */
+int rqa_job_footprint(const rqa_params *p, int64_t n_points, size_t *bytes);
+
+/* Submit a job.  d_series: n_points FP32 values in device memory, produced on
+ * hip_stream (the job starts only after the work enqueued there so far); the
+ * caller keeps it alive and unmodified until the job is retired by rqa_poll or
+ * rqa_wait.  RQA_EBUDGET if the job alone exceeds the budget; otherwise it is
+ * queued until its footprint fits.  *ticket identifies the job. */
+int rqa_submit(rqa_server *srv, const rqa_params *p, const float *d_series,
+               int64_t n_points, void *hip_stream, uint64_t *ticket);
+
+/* Poll (RQA_EAGAIN while running) or wait for a job; on success the job is
+ * retired and its result copied (histogram pointers may be NULL). */
+int rqa_poll(rqa_server *srv, uint64_t ticket, rqa_measures *out, uint64_t *diag,
+             uint64_t *vert, uint64_t *white, int64_t hist_len);
+int rqa_wait(rqa_server *srv, uint64_t ticket, rqa_measures *out, uint64_t *diag,
+             uint64_t *vert, uint64_t *white, int64_t hist_len);
+
+/* Drain all jobs and release the server. */
+void rqa_server_destroy(rqa_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQA_H */

@@ -1,0 +1,67 @@
+// Internal declarations shared by the host runtime and the kernel launchers of
+// librqa.  Not part of the public ABI (see include/rqa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "rqa.h"
+
+namespace rqa {
+
+// Parameters in the form the kernels consume.
+struct KParams {
+    int32_t m;
+    int32_t tau;
+    float eps;      // L1 / Linf threshold
+    float eps_sq;   // fl32(eps*eps), L2 threshold on the squared sum
+    int32_t norm;
+    int32_t theiler;
+};
+
+KParams make_kparams(const rqa_params &p);
+
+// One independent RQA problem inside a launch: a window of a device series.
+struct Job {
+    const float *series = nullptr;  // first point of the window (device)
+    int64_t n_points = 0;           // points in the window
+    int64_t n_vec = 0;              // delay vectors
+    uint64_t *hist = nullptr;       // device: 3*(n_vec+1) u64 -- diag | vert | white
+    int *flag = nullptr;            // device int: set to 1 if the window is not finite
+    void *scratch = nullptr;        // device: engine_job_scratch_bytes(*this) bytes
+    KParams kp{};                   // parameters of this job
+};
+
+// Device workspace owned by a handle (or a served job); grown on demand.
+struct Workspace {
+    int device = -1;
+    void *base = nullptr;
+    size_t bytes = 0;
+    ~Workspace();
+    int reserve(size_t need);   // RQA_OK / RQA_ENOMEM / RQA_EDEVICE
+};
+
+// Device scratch one job needs beyond its histograms and flag (segment
+// summaries and line-end records), and the per-launch scratch (work
+// descriptors and the work counter) of a launch over `njobs` jobs.
+size_t engine_job_scratch_bytes(const Job &job, int waves);
+size_t engine_launch_scratch_bytes(size_t njobs);
+
+// Enqueue the full hot path for all jobs on `stream` as one batched pass:
+// validation, zeroing, the fused tile kernel, the stitch/join kernel.
+// `launch_scratch` holds engine_launch_scratch_bytes(jobs.size()) device bytes;
+// `staging` is pinned host memory of the same size; `staging_free` (may be
+// null) is an event the engine waits on before rewriting `staging` and records
+// once the launch has consumed it.  waves = 0 / groups = 0 pick defaults.
+int engine_launch(const std::vector<Job> &jobs, void *launch_scratch, void *staging,
+                  hipEvent_t staging_free, int waves, int groups, hipStream_t stream);
+
+// Host FP64 measures from histograms of length n+1.
+void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
+                        int64_t n, const rqa_params &p, rqa_measures *out);
+
+int validate_params(const rqa_params &p);
+
+}  // namespace rqa

@@ -1,0 +1,408 @@
+// Served RQA: a request loop that admits independent jobs by device-memory
+// footprint and runs them with continuous batching.
+//
+// * The server owns one device pool of `budget` bytes, carved up by a
+//   first-fit allocator; a job is admitted (FIFO) when its footprint fits, so
+//   no hipMalloc happens on the request path.
+// * A worker thread groups all jobs admitted since the last launch into one
+//   batched launch of the engine on the next stream of a small pool; jobs that
+//   arrive while earlier launches run are launched on another stream and
+//   overlap with them on the device.
+// * Each launch copies its histograms into pinned host buffers and then fires a
+//   host callback that marks its jobs done and returns their device memory to
+//   the pool; the worker then admits more jobs.
+// Results are integer histograms, so a job's result does not depend on what
+// else runs beside it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rqa_internal.h"
+
+using namespace rqa;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// First-fit allocator over [0, size) with coalescing free list.
+class Pool {
+public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+enum JobState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
+
+struct ServedJob {
+    uint64_t ticket = 0;
+    rqa_params p{};
+    const float *series = nullptr;
+    int64_t n_points = 0;
+    int64_t n_vec = 0;
+    size_t footprint = 0;
+    size_t hist_bytes = 0;
+    size_t off = 0;
+    hipEvent_t ready = nullptr;    // recorded on the caller's stream at submit
+    uint64_t *host = nullptr;      // pinned: 3*(n+1) histograms + flag word
+    int state = kQueued;
+    int rc = RQA_OK;
+};
+
+struct Launch;
+
+}  // namespace
+
+struct rqa_server {
+    std::mutex mu;
+    std::condition_variable cv;        // worker wake-ups
+    std::condition_variable done_cv;   // job completions
+    int device = 0;
+    char *pool_base = nullptr;
+    size_t budget = 0;
+    Pool pool;
+    std::vector<hipStream_t> streams;
+    std::vector<char *> launch_scratch;   // per stream, device
+    std::vector<void *> staging;          // per stream, pinned host
+    std::vector<hipEvent_t> staging_free; // per stream: staging consumed
+    size_t next_stream = 0;
+    std::deque<ServedJob *> pending;
+    std::unordered_map<uint64_t, ServedJob *> jobs;
+    uint64_t next_ticket = 1;
+    int inflight = 0;
+    bool stop = false;
+    std::thread worker;
+};
+
+namespace {
+
+struct Launch {
+    rqa_server *srv;
+    std::vector<ServedJob *> jobs;
+};
+
+size_t job_hist_bytes(int64_t n_vec) {
+    return align256(sizeof(uint64_t) * 3 * static_cast<size_t>(n_vec + 1));
+}
+
+constexpr size_t kMaxBatch = 256;
+constexpr size_t kFlagBytes = 256;
+
+size_t job_scratch_bytes(const rqa_params &p, int64_t n_points, int64_t n_vec) {
+    Job one;
+    one.n_points = n_points;
+    one.n_vec = n_vec;
+    one.kp = make_kparams(p);
+    return align256(engine_job_scratch_bytes(one, 0));
+}
+
+void on_launch_done(void *arg) {
+    Launch *ln = static_cast<Launch *>(arg);
+    rqa_server *srv = ln->srv;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (ServedJob *j : ln->jobs) {
+            const int flag = static_cast<int>(j->host[3 * (j->n_vec + 1)]);
+            j->rc = (flag & 1) ? RQA_ENONFINITE : flag ? RQA_EDEVICE : RQA_OK;
+            j->state = flag ? kFailed : kDone;
+            srv->pool.release(j->off, j->footprint);
+        }
+        --srv->inflight;
+    }
+    srv->cv.notify_all();
+    srv->done_cv.notify_all();
+    delete ln;
+}
+
+// Launch every admissible queued job (FIFO, stop at the first that does not
+// fit).  Called with the lock held; HIP calls are made with it held, which is
+// fine because callbacks never call into HIP.
+void admit_and_launch(rqa_server *srv) {
+    std::vector<ServedJob *> batch;
+    while (!srv->pending.empty() && batch.size() < kMaxBatch) {
+        ServedJob *j = srv->pending.front();
+        size_t off = 0;
+        if (!srv->pool.alloc(j->footprint, &off)) break;
+        j->off = off;
+        srv->pending.pop_front();
+        batch.push_back(j);
+    }
+    if (batch.empty()) return;
+    const size_t slot = srv->next_stream;
+    hipStream_t st = srv->streams[slot];
+    srv->next_stream = (srv->next_stream + 1) % srv->streams.size();
+
+    std::vector<Job> ej;
+    ej.reserve(batch.size());
+    for (ServedJob *j : batch) {
+        hipStreamWaitEvent(st, j->ready, 0);
+        char *base = srv->pool_base + j->off;
+        Job e;
+        e.series = j->series;
+        e.n_points = j->n_points;
+        e.n_vec = j->n_vec;
+        e.hist = reinterpret_cast<uint64_t *>(base);
+        e.flag = reinterpret_cast<int *>(base + j->hist_bytes);
+        e.scratch = base + j->hist_bytes + kFlagBytes;
+        e.kp = make_kparams(j->p);
+        ej.push_back(e);
+        j->state = kRunning;
+    }
+    int rc = engine_launch(ej, srv->launch_scratch[slot], srv->staging[slot],
+                           srv->staging_free[slot], 0, 0, st);
+    for (size_t k = 0; k < batch.size() && rc == RQA_OK; ++k) {
+        ServedJob *j = batch[k];
+        const size_t hb = sizeof(uint64_t) * 3 * static_cast<size_t>(j->n_vec + 1);
+        if (hipMemcpyAsync(j->host, ej[k].hist, hb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(j->host + 3 * (j->n_vec + 1), ej[k].flag, sizeof(int),
+                           hipMemcpyDeviceToHost, st) != hipSuccess)
+            rc = RQA_EDEVICE;
+    }
+    Launch *ln = new Launch{srv, batch};
+    if (rc == RQA_OK && hipLaunchHostFunc(st, on_launch_done, ln) == hipSuccess) {
+        ++srv->inflight;
+        return;
+    }
+    // Launch failed: fail the jobs and wait for the stream before releasing.
+    hipStreamSynchronize(st);
+    for (ServedJob *j : batch) {
+        j->state = kFailed;
+        j->rc = rc == RQA_OK ? RQA_EDEVICE : rc;
+        srv->pool.release(j->off, j->footprint);
+    }
+    delete ln;
+    srv->done_cv.notify_all();
+}
+
+void worker_main(rqa_server *srv) {
+    hipSetDevice(srv->device);
+    std::unique_lock<std::mutex> lk(srv->mu);
+    while (true) {
+        srv->cv.wait(lk, [srv] { return srv->stop || !srv->pending.empty(); });
+        if (srv->stop && srv->pending.empty()) break;
+        const size_t before = srv->pending.size();
+        admit_and_launch(srv);
+        if (srv->pending.size() == before) {
+            // Nothing fit: wait for a completion (or a stop request).
+            srv->cv.wait(lk, [srv, before] {
+                return srv->stop || srv->inflight == 0 || srv->pending.size() != before;
+            });
+            if (srv->inflight == 0 && srv->pending.size() == before && !srv->stop) {
+                // Head job cannot fit even in an empty pool (guarded at submit).
+                ServedJob *j = srv->pending.front();
+                srv->pending.pop_front();
+                j->state = kFailed;
+                j->rc = RQA_EBUDGET;
+                srv->done_cv.notify_all();
+            }
+        }
+    }
+}
+
+int collect(rqa_server *srv, ServedJob *j, rqa_measures *out, uint64_t *diag, uint64_t *vert,
+            uint64_t *white) {
+    const int64_t n = j->n_vec;
+    int rc = j->rc;
+    if (rc == RQA_OK) {
+        const uint64_t *hd = j->host, *hv = hd + (n + 1), *hw = hv + (n + 1);
+        if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * (n + 1));
+        if (vert) std::memcpy(vert, hv, sizeof(uint64_t) * (n + 1));
+        if (white) std::memcpy(white, hw, sizeof(uint64_t) * (n + 1));
+        if (out) measures_from_hist(hd, hv, hw, n, j->p, out);
+    }
+    srv->jobs.erase(j->ticket);
+    hipHostFree(j->host);
+    hipEventDestroy(j->ready);
+    delete j;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rqa_job_footprint(const rqa_params *p, int64_t n_points, size_t *bytes) {
+    if (!p || !bytes) return RQA_EINVAL;
+    int rc = validate_params(*p);
+    if (rc != RQA_OK) return rc;
+    const int64_t nv = n_points - static_cast<int64_t>(p->m - 1) * p->tau;
+    if (nv < 1) return RQA_ETOOSHORT;
+    *bytes = job_hist_bytes(nv) + kFlagBytes + job_scratch_bytes(*p, n_points, nv);
+    return RQA_OK;
+}
+
+int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams) {
+    if (!out || budget_bytes < 4096 || streams < 1 || streams > 16) return RQA_EINVAL;
+    std::unique_ptr<rqa_server> srv(new (std::nothrow) rqa_server);
+    if (!srv) return RQA_ENOMEM;
+    if (hipGetDevice(&srv->device) != hipSuccess) return RQA_EDEVICE;
+    void *base = nullptr;
+    if (hipMalloc(&base, budget_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return RQA_ENOMEM;
+    }
+    srv->pool_base = static_cast<char *>(base);
+    srv->budget = budget_bytes;
+    srv->pool.reset(budget_bytes);
+    const size_t ls = align256(engine_launch_scratch_bytes(kMaxBatch));
+    bool ok = true;
+    for (int32_t k = 0; k < streams && ok; ++k) {
+        hipStream_t st = nullptr;
+        void *d = nullptr, *h = nullptr;
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (ok) srv->streams.push_back(st);
+        ok = ok && hipMalloc(&d, ls) == hipSuccess;
+        if (ok) srv->launch_scratch.push_back(static_cast<char *>(d));
+        ok = ok && hipHostMalloc(&h, ls, hipHostMallocDefault) == hipSuccess;
+        if (ok) srv->staging.push_back(h);
+        hipEvent_t ev = nullptr;
+        ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (ok) srv->staging_free.push_back(ev);
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        for (hipStream_t s : srv->streams) hipStreamDestroy(s);
+        for (char *d : srv->launch_scratch) hipFree(d);
+        for (void *h : srv->staging) hipHostFree(h);
+        for (hipEvent_t e : srv->staging_free) hipEventDestroy(e);
+        hipFree(base);
+        return RQA_ENOMEM;
+    }
+    rqa_server *raw = srv.release();
+    raw->worker = std::thread(worker_main, raw);
+    *out = raw;
+    return RQA_OK;
+}
+
+int rqa_submit(rqa_server *srv, const rqa_params *p, const float *d_series, int64_t n_points,
+               void *hip_stream, uint64_t *ticket) {
+    if (!srv || !p || !d_series || !ticket || n_points < 0) return RQA_EINVAL;
+    size_t fp = 0;
+    int rc = rqa_job_footprint(p, n_points, &fp);
+    if (rc != RQA_OK) return rc;
+    if (fp > srv->budget) return RQA_EBUDGET;
+    ServedJob *j = new (std::nothrow) ServedJob;
+    if (!j) return RQA_ENOMEM;
+    j->p = *p;
+    j->series = d_series;
+    j->n_points = n_points;
+    j->n_vec = n_points - static_cast<int64_t>(p->m - 1) * p->tau;
+    j->footprint = fp;
+    j->hist_bytes = job_hist_bytes(j->n_vec);
+    if (hipHostMalloc(reinterpret_cast<void **>(&j->host),
+                      sizeof(uint64_t) * (3 * static_cast<size_t>(j->n_vec + 1) + 1),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete j;
+        return RQA_ENOMEM;
+    }
+    std::memset(j->host, 0, sizeof(uint64_t) * (3 * static_cast<size_t>(j->n_vec + 1) + 1));
+    if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(j->ready, static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
+        hipHostFree(j->host);
+        delete j;
+        return RQA_EDEVICE;
+    }
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        j->ticket = srv->next_ticket++;
+        srv->jobs[j->ticket] = j;
+        srv->pending.push_back(j);
+        *ticket = j->ticket;
+    }
+    srv->cv.notify_all();
+    return RQA_OK;
+}
+
+int rqa_poll(rqa_server *srv, uint64_t ticket, rqa_measures *out, uint64_t *diag, uint64_t *vert,
+             uint64_t *white, int64_t hist_len) {
+    if (!srv) return RQA_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(ticket);
+    if (it == srv->jobs.end()) return RQA_ENOTFOUND;
+    ServedJob *j = it->second;
+    if ((diag || vert || white) && hist_len < j->n_vec + 1) return RQA_ESIZE;
+    if (j->state == kQueued || j->state == kRunning) return RQA_EAGAIN;
+    return collect(srv, j, out, diag, vert, white);
+}
+
+int rqa_wait(rqa_server *srv, uint64_t ticket, rqa_measures *out, uint64_t *diag, uint64_t *vert,
+             uint64_t *white, int64_t hist_len) {
+    if (!srv) return RQA_EINVAL;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->jobs.find(ticket);
+    if (it == srv->jobs.end()) return RQA_ENOTFOUND;
+    ServedJob *j = it->second;
+    if ((diag || vert || white) && hist_len < j->n_vec + 1) return RQA_ESIZE;
+    srv->done_cv.wait(lk, [j] { return j->state == kDone || j->state == kFailed; });
+    return collect(srv, j, out, diag, vert, white);
+}
+
+void rqa_server_destroy(rqa_server *srv) {
+    if (!srv) return;
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        srv->done_cv.wait(lk, [srv] { return srv->pending.empty() && srv->inflight == 0; });
+        srv->stop = true;
+    }
+    srv->cv.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    for (hipStream_t s : srv->streams) {
+        hipStreamSynchronize(s);
+        hipStreamDestroy(s);
+    }
+    for (char *d : srv->launch_scratch) hipFree(d);
+    for (void *h : srv->staging) hipHostFree(h);
+    for (hipEvent_t e : srv->staging_free) hipEventDestroy(e);
+    for (auto &kv : srv->jobs) {
+        hipHostFree(kv.second->host);
+        hipEventDestroy(kv.second->ready);
+        delete kv.second;
+    }
+    hipFree(srv->pool_base);
+    delete srv;
+}
+
+}  // extern "C"

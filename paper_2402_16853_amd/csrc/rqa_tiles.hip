@@ -1,0 +1,878 @@
+// Fused RQA engine for gfx950: recurrence predicate, diagonal / vertical /
+// white-vertical run extraction and histogram recombination in one pass over
+// the upper triangle of the recurrence matrix, which is never stored.
+//
+// Mapping of the paper's method (Sect. 4):
+//  * operator I (similarity of one vector pair) -- evaluated once per unique pair
+//    i < j with j - i >= max(theiler, 1): the matrix is symmetric, so the lower
+//    triangle is recovered by mirroring (Sect. 4.2 notes that a symmetric matrix
+//    needs only N-1 diagonals);
+//  * operators II and III (lines along one diagonal / one column) -- run-length
+//    state machines over 64-bit bit-words of 64x64 tiles;
+//  * divide & recombine with carry-over (Sect. 4.1) -- open runs are carried
+//    across tile edges in registers (left to right) and through LDS between the
+//    waves of a workgroup (top to bottom); runs that touch the top or bottom edge
+//    of a workgroup's strip are summarised and joined by the stitch kernel.
+//
+// Geometry.  n delay vectors, w' = max(theiler, 1).  U = {(i,j): j - i >= w'}.
+// A workgroup of W waves owns a strip of H = 64*W consecutive rows; wave w owns
+// rows R = R0 + 64w .. R+63, one row per lane, and walks the 64-column tiles
+// c = c0 .. c_last of its strip left to right.  The waves run as a pipeline with
+// one tile of lag per wave (one barrier per step), so wave w consumes at step t
+// what wave w-1 produced for the same tile at step t-1.
+//
+// Full-matrix lines from U:
+//  * a diagonal k >= w' of U and its mirror -k: each run counted twice;
+//  * column j of the full matrix = [column j of U: rows 0..j-w'] ++ [middle] ++
+//    [row j of U: columns j+w'..n-1], the middle being the Theiler band (white,
+//    theiler >= 1) or the single recurrent cell (j,j) (theiler = 0).  Runs inside
+//    either segment are counted where they are found; the trailing run of the
+//    column segment, the middle and the leading run of the row segment are
+//    merged by the join step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "rqa_internal.h"
+
+namespace rqa {
+
+KParams make_kparams(const rqa_params &p) {
+    KParams k;
+    k.m = p.m;
+    k.tau = p.tau;
+    k.eps = p.eps;
+    volatile float e = p.eps;   // one FP32 rounding of eps*eps, no contraction
+    k.eps_sq = e * e;
+    k.norm = p.norm;
+    k.theiler = p.theiler;
+    return k;
+}
+
+namespace {
+
+constexpr int kMaxWaves = 16;
+constexpr int kCapD = 1024;    // LDS bins for diagonal lengths < kCapD
+constexpr int kCapV = 1024;    // LDS bins for vertical lengths < kCapV
+constexpr int kCapW = 6144;    // LDS bins for white-vertical lengths < kCapW
+constexpr int kMaxM = 6;       // embedding dimensions held in registers
+constexpr int kStitchThreads = 256;
+
+// Device-side description of one job (one series or window).
+struct JobDesc {
+    const float *s;            // series (n_points values)
+    const float *tail;         // coordinates of the last column tile, zero padded
+    unsigned long long *hd;    // histograms, n+1 entries each
+    unsigned long long *hv;
+    unsigned long long *hw;
+    int *flag;                 // non-finite flag
+    uint32_t *lead;            // leading run of each row of U: len | color<<31
+    uint16_t *vfirst;          // per (strip, column): first run len | color<<15
+    uint16_t *vlast;           // per (strip, column): last run len | color<<15
+    uint16_t *dfirst;          // per (strip, diagonal): black run at the top edge
+    uint16_t *dlast;           // per (strip, diagonal): black run at the bottom edge
+    int64_t n_points;
+    int32_t n;                 // delay vectors
+    int32_t m, tau, norm, theiler, wp;
+    float thr;                 // eps (L1, Linf) or fl32(eps*eps) (L2)
+    int32_t H;                 // strip height
+    int32_t nstrips;
+    int32_t c_last;            // last column tile (n-1)/64
+    int32_t tail_len;          // floats in tail
+    int32_t strip_base;        // first work item of this job within its group
+    int32_t stitch_block0;     // first stitch block of this job
+};
+
+struct GroupDesc {
+    int32_t job0, job1;        // jobs [job0, job1) of the descriptor table
+    int32_t items;             // total strips of the group
+    int32_t pad;
+};
+
+__host__ __device__ inline int64_t strip_offset(int32_t s, int32_t n, int32_t wp, int32_t H) {
+    // sum_{s' < s} (n - wp - s' H): entries of the strips before s
+    return (int64_t)s * (n - wp) - (int64_t)H * ((int64_t)s * (s - 1) / 2);
+}
+
+// ---------------------------------------------------------------------------
+// Bit-word helpers (64-bit words split in two VGPRs; bit p = position p along a
+// line).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mk64(uint32_t lo, uint32_t hi) {
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t range_mask(uint32_t lo, uint32_t hi) {
+    // bits [lo, hi), 0 <= lo <= hi <= 64
+    const uint64_t a = lo >= 64 ? 0ull : (~0ull << lo);
+    const uint64_t b = hi >= 64 ? ~0ull : ((1ull << hi) - 1ull);
+    return a & b;
+}
+
+__device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int d) {
+    return (uint32_t)__shfl_xor((int)v, d, 64);
+}
+
+// One butterfly stage of the bit-matrix transpose within 32-bit halves: lanes l
+// and l^D exchange the bit blocks selected by M (positions whose D-bit is 0) and
+// ~M.
+template <int D, uint32_t M>
+__device__ __forceinline__ void transpose_stage(uint32_t &lo, uint32_t &hi, int lane) {
+    const bool up = lane & D;
+    const uint32_t sl = up ? (lo & M) : (lo & ~M);
+    const uint32_t sh = up ? (hi & M) : (hi & ~M);
+    const uint32_t rl = shfl_xor32(sl, D);
+    const uint32_t rh = shfl_xor32(sh, D);
+    if (up) {
+        lo = (lo & ~M) | (rl >> D);
+        hi = (hi & ~M) | (rh >> D);
+    } else {
+        lo = (lo & M) | (rl << D);
+        hi = (hi & M) | (rh << D);
+    }
+}
+
+// In-register transpose of a 64x64 bit matrix held one row per lane: on return
+// lane l holds column l (bit r = old lane r's bit l).  Six butterfly stages; at
+// stage d the d-bit of the lane index is exchanged with the d-bit of the bit
+// position.
+__device__ __forceinline__ void transpose64(uint32_t &lo, uint32_t &hi, int lane) {
+    {   // d = 32: swap the 32-bit halves across lanes l and l^32
+        const bool up = lane & 32;
+        const uint32_t send = up ? lo : hi;
+        const uint32_t recv = shfl_xor32(send, 32);
+        if (up) lo = recv; else hi = recv;
+    }
+    transpose_stage<16, 0x0000FFFFu>(lo, hi, lane);
+    transpose_stage<8, 0x00FF00FFu>(lo, hi, lane);
+    transpose_stage<4, 0x0F0F0F0Fu>(lo, hi, lane);
+    transpose_stage<2, 0x33333333u>(lo, hi, lane);
+    transpose_stage<1, 0x55555555u>(lo, hi, lane);
+}
+
+// 64-bit rotate right by r (0..63).
+__device__ __forceinline__ void rotr64(uint32_t &lo, uint32_t &hi, uint32_t r) {
+    if (r & 32) { const uint32_t t = lo; lo = hi; hi = t; }
+    const uint32_t s = r & 31;
+    if (s) {
+        const uint32_t nl = __builtin_amdgcn_alignbit(hi, lo, s);
+        const uint32_t nh = __builtin_amdgcn_alignbit(lo, hi, s);
+        lo = nl;
+        hi = nh;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Run state machine.  A line is cut into segments; `Run` is the open run at the
+// current position: colour (1 = recurrent), length so far, and whether it is the
+// first run of the current segment (then it is recorded instead of counted).
+// ---------------------------------------------------------------------------
+struct Run {
+    uint32_t color;
+    uint32_t len;
+    uint32_t first;
+};
+
+__device__ __forceinline__ uint32_t pack_run(const Run &r) {
+    return (r.len & 0xFFFFu) | (r.color << 16) | (r.first << 17);
+}
+__device__ __forceinline__ Run unpack_run(uint32_t v) {
+    return Run{(v >> 16) & 1u, v & 0xFFFFu, (v >> 17) & 1u};
+}
+
+struct Bins {
+    uint32_t *d, *v, *w;
+};
+
+// Count `wt` lines of length len: LDS bin below the cap, else the global
+// histogram.  A length beyond the histogram (n) cannot occur for a correct run
+// and is reported through bit 1 of the job flag instead of being written.
+__device__ __forceinline__ void emit(uint32_t *bins, int cap, unsigned long long *glob, uint32_t len,
+                                     uint32_t wt, uint32_t n, int *flag) {
+    if (len < (uint32_t)cap && len <= n)
+        atomicAdd(bins + len, wt);
+    else if (len <= n)
+        atomicAdd(glob + len, (unsigned long long)wt);
+    else
+        atomicOr(flag, 2);
+}
+
+enum LineKind { kHoriz = 0, kVert = 1, kDiag = 2 };
+
+struct LineCtx {
+    const JobDesc *jd;
+    Bins bins;
+    int64_t sum_idx;    // summary index of this line in this strip (vert / diag)
+    bool sum_ok;        // summary slot exists (diagonal inside the strip's range)
+    uint32_t row;       // row index (horizontal)
+};
+
+// A run of colour `c` and length `len` has ended.
+template <int KIND>
+__device__ __forceinline__ void finish_run(const LineCtx &lc, uint32_t c, uint32_t len, uint32_t first) {
+    const JobDesc &j = *lc.jd;
+    if (KIND == kDiag) {
+        if (first) {
+            if (lc.sum_ok) j.dfirst[lc.sum_idx] = (uint16_t)(c ? len : 0u);
+        } else if (c) {
+            emit(lc.bins.d, kCapD, j.hd, len, 2u, (uint32_t)j.n, j.flag);
+        }
+    } else if (KIND == kVert) {
+        if (first)
+            j.vfirst[lc.sum_idx] = (uint16_t)(len | (c << 15));
+        else if (c)
+            emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.n, j.flag);
+        else
+            emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.n, j.flag);
+    } else {
+        if (first)
+            j.lead[lc.row] = len | (c << 31);
+        else if (c)
+            emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.n, j.flag);
+        else
+            emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.n, j.flag);
+    }
+}
+
+// Advance `st` over bits [lo, hi) of x, finishing every run that ends there.
+template <int KIND>
+__device__ __forceinline__ void run_segment(uint64_t x, uint32_t lo, uint32_t hi, Run &st,
+                                            const LineCtx &lc) {
+    if (lo >= hi) return;
+    const uint64_t win = range_mask(lo, hi);
+    uint32_t pos = lo;
+    while (true) {
+        const uint64_t diff = (st.color ? ~x : x) & win & (~0ull << pos);
+        if (diff == 0) {
+            st.len += hi - pos;
+            break;
+        }
+        const uint32_t p = (uint32_t)__builtin_ctzll(diff);
+        finish_run<KIND>(lc, st.color, st.len + (p - pos), st.first);
+        st.first = 0;
+        st.color ^= 1u;
+        st.len = 0;
+        pos = p;
+    }
+}
+
+// Series pointer in the constant address space: loads through it with a
+// wave-uniform address become scalar (s_load) loads, so the column coordinates
+// arrive in SGPRs and feed the VALU as scalar operands.
+typedef const __attribute__((address_space(4))) float *ConstF;
+
+__device__ __forceinline__ ConstF to_const(const float *p) { return (ConstF)(p); }
+
+// ---------------------------------------------------------------------------
+// Recurrence predicate for one column against the 64 rows of a wave.
+// Returns a word whose bit 31 is set when the pair is NOT recurrent: the sign of
+// fl(thr - a) is set exactly when a > thr (IEEE subtraction of two finite floats
+// is zero only for equal operands).  a is accumulated in FP32, coordinates in
+// ascending order, no FMA.
+// ---------------------------------------------------------------------------
+template <int NORM, int M>
+__device__ __forceinline__ uint32_t nonrec_sign(ConstF col, int tau, const float *xr, float thr) {
+    float a;
+    if (NORM == RQA_NORM_L1) {
+        a = fabsf(col[0] - xr[0]);
+#pragma unroll
+        for (int k = 1; k < M; ++k) a = a + fabsf(col[k * tau] - xr[k]);
+    } else if (NORM == RQA_NORM_L2) {
+        const float d = col[0] - xr[0];
+        a = d * d;
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+            const float e = col[k * tau] - xr[k];
+            a = a + e * e;
+        }
+    } else {
+        a = fabsf(col[0] - xr[0]);
+#pragma unroll
+        for (int k = 1; k < M; ++k) a = fmaxf(a, fabsf(col[k * tau] - xr[k]));
+    }
+    return __float_as_uint(thr - a);
+}
+
+// Generic embedding dimension: row coordinates read from memory.
+template <int NORM>
+__device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__restrict__ row,
+                                                    int m, int tau, float thr) {
+    float a;
+    if (NORM == RQA_NORM_L1) {
+        a = fabsf(col[0] - row[0]);
+        for (int k = 1; k < m; ++k) a = a + fabsf(col[(int64_t)k * tau] - row[(int64_t)k * tau]);
+    } else if (NORM == RQA_NORM_L2) {
+        const float d = col[0] - row[0];
+        a = d * d;
+        for (int k = 1; k < m; ++k) {
+            const float e = col[(int64_t)k * tau] - row[(int64_t)k * tau];
+            a = a + e * e;
+        }
+    } else {
+        a = fabsf(col[0] - row[0]);
+        for (int k = 1; k < m; ++k) a = fmaxf(a, fabsf(col[(int64_t)k * tau] - row[(int64_t)k * tau]));
+    }
+    return __float_as_uint(thr - a);
+}
+
+// Recurrence bits of one 64x64 tile for this lane's row: bit b <-> column
+// jbase + b.  `cols` points at the coordinate of column jbase (uniform).  The 64
+// columns are taken in four chunks of 16 (highest first), each fully unrolled,
+// so that at most 16*m column coordinates are live in SGPRs.
+template <int NORM, int M>
+__device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
+                                          const float *__restrict__ rowp, int m, float thr,
+                                          uint32_t &lo, uint32_t &hi) {
+#pragma unroll 1
+    for (int half = 1; half >= 0; --half) {
+        uint32_t acc = 0;
+#pragma unroll 1
+        for (int sub = 1; sub >= 0; --sub) {
+            const int b0 = half * 32 + sub * 16;
+            ConstF cb = cols + b0;
+            if (M > 0) {
+#pragma unroll
+                for (int b = 15; b >= 0; --b)
+                    acc = __builtin_amdgcn_alignbit(acc, nonrec_sign<NORM, M>(cb + b, tau, xr, thr), 31);
+            } else {
+                for (int b = 15; b >= 0; --b)
+                    acc = __builtin_amdgcn_alignbit(
+                        acc, nonrec_sign_dyn<NORM>(cb + b, rowp, m, tau, thr), 31);
+            }
+        }
+        if (half) hi = ~acc; else lo = ~acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 1: per-job preparation -- zero the histograms, flag non-finite input,
+// build the zero-padded tail of the last column tile, reset work counters.
+// grid.y = job index.
+// ---------------------------------------------------------------------------
+__global__ void k_prepare(const JobDesc *__restrict__ jobs) {
+    const JobDesc &j = jobs[blockIdx.y];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t hl = (int64_t)j.n + 1;
+    for (int64_t t = tid; t < hl; t += stride) {
+        j.hd[t] = 0ull;
+        j.hv[t] = 0ull;
+        j.hw[t] = 0ull;
+    }
+    bool bad = false;
+    for (int64_t t = tid; t < j.n_points; t += stride) bad |= !__builtin_isfinite(j.s[t]);
+    if (bad) atomicOr(j.flag, 1);   // bit 0: non-finite input
+    const int64_t base = (int64_t)j.c_last * 64;
+    float *tail = const_cast<float *>(j.tail);
+    for (int64_t t = tid; t < j.tail_len; t += stride)
+        tail[t] = base + t < j.n_points ? j.s[base + t] : 0.0f;
+}
+
+// Reset the non-finite flags and the work counters (runs before k_prepare).
+__global__ void k_reset(const JobDesc *__restrict__ jobs, int njobs, int *counters, int ncounters) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < njobs) *jobs[t].flag = 0;
+    if (t < ncounters) counters[t] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 2: the fused tile pass.  Persistent workgroups pull (job, strip) work
+// items of one (norm, m) group from a counter.
+// ---------------------------------------------------------------------------
+struct StripLds {
+    uint32_t bd[kCapD];
+    uint32_t bv[kCapV];
+    uint32_t bw[kCapW];
+    uint32_t vslot[2][kMaxWaves][64];
+    uint32_t dslot[2][kMaxWaves][64];
+    int item;
+};
+
+__device__ void flush_bins(StripLds &L, const JobDesc &j) {
+    const int hl = j.n + 1;
+    for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
+        if (t < kCapD) {
+            const uint32_t v = L.bd[t];
+            if (v) { if (t < hl) atomicAdd(j.hd + t, (unsigned long long)v); L.bd[t] = 0; }
+        }
+        if (t < kCapV) {
+            const uint32_t v = L.bv[t];
+            if (v) { if (t < hl) atomicAdd(j.hv + t, (unsigned long long)v); L.bv[t] = 0; }
+        }
+        const uint32_t v = L.bw[t];
+        if (v) { if (t < hl) atomicAdd(j.hw + t, (unsigned long long)v); L.bw[t] = 0; }
+    }
+}
+
+template <int NORM, int M>
+__device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int nw = blockDim.x >> 6;
+    const int n = j.n, wp = j.wp, H = j.H, tau = j.tau;
+    const int R0 = strip * H;
+    const int R = R0 + 64 * wave;
+    const int i = R + lane;                      // this lane's row
+    const int c0 = (R0 + wp) >> 6;
+    const int T = j.c_last - c0 + 1;             // tiles of the strip
+    const bool wave_has_u = R + wp <= n - 1;     // some row of this wave has U cells
+    const int cfirst = (R + wp) >> 6;            // first tile with U cells for this wave
+    const int64_t soff = strip_offset(strip, n, wp, H);
+
+    // Row coordinates of this lane (clamped for rows past the end).
+    const int irow = i < n ? i : n - 1;
+    const float *rowp = j.s + irow;
+    float xr[M > 0 ? M : 1];
+#pragma unroll
+    for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? rowp[(int64_t)k * tau] : 0.0f;
+
+    Bins bins{L.bd, L.bv, L.bw};
+    Run hs{0, 0, 0};          // horizontal run of this lane's row
+    bool hstarted = false;
+    Run left{0, 0, 0};        // diagonal carry from the previous tile (upper part end)
+
+    const int nsteps = T + nw - 1;
+    for (int step = 0; step < nsteps; ++step) {
+        const int t = step - wave;
+        const int c = c0 + t;
+        if (wave_has_u && t >= 0 && t < T && c >= cfirst) {
+            const int jbase = c * 64;
+            const ConstF cols = to_const((c == j.c_last) ? j.tail : j.s + jbase);
+            uint32_t xlo, xhi;
+            tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, xlo, xhi);
+
+            // Valid cells of this row: columns [i + wp, n-1], rows < n.
+            int lo_v = i + wp - jbase;
+            lo_v = lo_v < 0 ? 0 : lo_v;
+            if (i >= n || lo_v > 64) lo_v = 64;
+            int hi_v = n - jbase;
+            hi_v = hi_v > 64 ? 64 : hi_v;
+            const uint64_t vmask = lo_v < hi_v ? range_mask(lo_v, hi_v) : 0ull;
+            uint64_t X = mk64(xlo, xhi) & vmask;
+            xlo = (uint32_t)X;
+            xhi = (uint32_t)(X >> 32);
+
+            // ---- horizontal runs (row i of U) ----
+            if (lo_v < hi_v) {
+                if (!hstarted) {
+                    hstarted = true;
+                    hs = Run{(uint32_t)((X >> lo_v) & 1ull), 0u, 1u};
+                }
+                LineCtx lc{&j, bins, 0, false, (uint32_t)i};
+                run_segment<kHoriz>(X, (uint32_t)lo_v, (uint32_t)hi_v, hs, lc);
+            }
+
+            const bool any = __ballot(X != 0ull) != 0ull;
+
+            // ---- vertical runs (columns of U) ----
+            {
+                uint32_t ylo = xlo, yhi = xhi;
+                if (any) transpose64(ylo, yhi, lane);
+                else { ylo = 0; yhi = 0; }
+                const uint64_t Y = mk64(ylo, yhi);
+                const int jc = jbase + lane;
+                const int e = jc - wp - R;            // last valid local row of column jc
+                if (jc <= n - 1 && e >= 0) {
+                    const uint32_t vhi = e >= 63 ? 64u : (uint32_t)(e + 1);
+                    Run st;
+                    if (wave == 0) st = Run{(uint32_t)(Y & 1ull), 0u, 1u};
+                    else st = unpack_run(L.vslot[(step - 1) & 1][wave - 1][lane]);
+                    const int64_t sidx = soff + (jc - R0 - wp);
+                    LineCtx lc{&j, bins, sidx, true, 0u};
+                    run_segment<kVert>(Y, 0u, vhi, st, lc);
+                    if (e <= 63 || wave == nw - 1) {
+                        const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
+                        j.vlast[sidx] = pk;
+                        if (st.first) j.vfirst[sidx] = pk;
+                    } else {
+                        L.vslot[step & 1][wave][lane] = pack_run(st);
+                    }
+                }
+            }
+
+            // ---- diagonal runs ----
+            {
+                uint32_t zlo = xlo, zhi = xhi;
+                if (any) {
+                    rotr64(zlo, zhi, (uint32_t)lane);
+                    transpose64(zlo, zhi, lane);
+                } else {
+                    zlo = 0;
+                    zhi = 0;
+                }
+                const uint64_t D = mk64(zlo, zhi);
+                const int q = lane;
+                const int kup = jbase + q - R;          // diagonal of the upper part
+                const int klo = kup - 64;               // diagonal of the lower part
+                Run up;
+                if (wave == 0) up = Run{(uint32_t)(D & 1ull), 0u, 1u};
+                else up = unpack_run(L.dslot[(step - 1) & 1][wave - 1][lane]);
+                {
+                    const bool ok = kup >= wp && kup <= n - 1 - R0;
+                    LineCtx lc{&j, bins, soff + (kup - wp), ok, 0u};
+                    run_segment<kDiag>(D, 0u, (uint32_t)(64 - q), up, lc);
+                }
+                Run lw = left;
+                {
+                    const bool ok = klo >= wp && klo <= n - 1 - R0;
+                    LineCtx lc{&j, bins, soff + (klo - wp), ok, 0u};
+                    run_segment<kDiag>(D, (uint32_t)(64 - q), 64u, lw, lc);
+                    if (wave < nw - 1) {
+                        L.dslot[step & 1][wave][lane] = pack_run(lw);
+                    } else if (ok && R0 + H + klo <= n - 1) {
+                        const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
+                        j.dlast[soff + (klo - wp)] = b;
+                        if (lw.first) j.dfirst[soff + (klo - wp)] = b;
+                    }
+                }
+                left = up;
+            }
+        }
+        __syncthreads();
+    }
+
+    if (wave_has_u) {
+        // Rows end at column n-1: their last run is complete.
+        if (hstarted) {
+            LineCtx lc{&j, bins, 0, false, (uint32_t)i};
+            finish_run<kHoriz>(lc, hs.color, hs.len, hs.first);
+        }
+        // Upper parts that left the last tile on its right edge end at the border.
+        const int kup = j.c_last * 64 + lane - R;
+        const bool ok = kup >= wp && kup <= n - 1 - R0;
+        LineCtx lc{&j, bins, soff + (kup - wp), ok, 0u};
+        if (left.color || left.first) finish_run<kDiag>(lc, left.color, left.len, left.first);
+    }
+}
+
+template <int NORM, int M>
+__global__ void __launch_bounds__(1024) k_tiles(const JobDesc *__restrict__ jobs,
+                                                const GroupDesc *__restrict__ groups, int g,
+                                                int *counters) {
+    __shared__ StripLds L;
+    const GroupDesc gd = groups[g];
+    for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
+        if (t < kCapD) L.bd[t] = 0;
+        if (t < kCapV) L.bv[t] = 0;
+        L.bw[t] = 0;
+    }
+    __syncthreads();
+    while (true) {
+        if (threadIdx.x == 0) L.item = atomicAdd(counters + g, 1);
+        __syncthreads();
+        const int item = L.item;
+        __syncthreads();
+        if (item >= gd.items) break;
+        // locate the job: largest job index in [job0, job1) with strip_base <= item
+        int lo = gd.job0, hi = gd.job1 - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].strip_base <= item) lo = mid; else hi = mid - 1;
+        }
+        const JobDesc j = jobs[lo];
+        process_strip<NORM, M>(j, item - j.strip_base, L);
+        __syncthreads();
+        flush_bins(L, j);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel 3: stitch and join.  One thread per line: columns j in [0, n) fold their
+// per-strip segment summaries and join the trailing run of column j of U with
+// the middle and the leading run of row j of U; diagonals k in [w', n) fold
+// their summaries.  Runs crossing strip edges are counted here.
+// ---------------------------------------------------------------------------
+struct StitchLds {
+    uint32_t bd[kCapD];
+    uint32_t bv[kCapV];
+    uint32_t bw[kCapW];
+};
+
+__device__ __forceinline__ void emit_line(StitchLds &L, const JobDesc &j, uint32_t color,
+                                          uint32_t len) {
+    if (len == 0) return;
+    if (color) emit(L.bv, kCapV, j.hv, len, 1u, (uint32_t)j.n, j.flag);
+    else emit(L.bw, kCapW, j.hw, len, 1u, (uint32_t)j.n, j.flag);
+}
+
+__global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__restrict__ jobs,
+                                                           int njobs) {
+    __shared__ StitchLds L;
+    for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
+        if (t < kCapD) L.bd[t] = 0;
+        if (t < kCapV) L.bv[t] = 0;
+        L.bw[t] = 0;
+    }
+    __syncthreads();
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].stitch_block0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const JobDesc &j = jobs[lo];
+    const int n = j.n, wp = j.wp, H = j.H;
+    const int64_t line = (int64_t)(blockIdx.x - j.stitch_block0) * blockDim.x + threadIdx.x;
+
+    if (line < n) {
+        // ---- column j of the full matrix ----
+        const int col = (int)line;
+        uint32_t oc = 0, ol = 0;   // open run after folding column `col` of U
+        if (col >= wp) {
+            const int s_last = (col - wp) / H;
+            for (int s = 0; s <= s_last; ++s) {
+                const uint32_t Ls = s < s_last ? (uint32_t)H : (uint32_t)(col - wp - s * H + 1);
+                const int64_t idx = strip_offset(s, n, wp, H) + (col - s * H - wp);
+                const uint32_t f = j.vfirst[idx], l = j.vlast[idx];
+                const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
+                if (fl == Ls) {   // the segment is one run
+                    if (ol && oc == fc) ol += Ls;
+                    else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
+                } else {
+                    if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
+                    else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
+                    oc = l >> 15;
+                    ol = l & 0x7FFFu;
+                }
+            }
+        }
+        // join: [trailing run of the column of U] [middle] [leading run of row col of U]
+        uint32_t mc, ml;
+        if (j.theiler == 0) { mc = 1; ml = 1; }
+        else {
+            const int w = j.theiler;
+            const int up = col < w - 1 ? col : w - 1;
+            const int dn = (n - 1 - col) < w - 1 ? (n - 1 - col) : w - 1;
+            mc = 0;
+            ml = (uint32_t)(up + 1 + dn);
+        }
+        if (ol && oc == mc) ol += ml;
+        else { emit_line(L, j, oc, ol); oc = mc; ol = ml; }
+        if (col + wp <= n - 1) {
+            const uint32_t ld = j.lead[col];
+            const uint32_t hc = ld >> 31, hl = ld & 0x7FFFFFFFu;
+            if (oc == hc) ol += hl;
+            else { emit_line(L, j, oc, ol); oc = hc; ol = hl; }
+        }
+        emit_line(L, j, oc, ol);
+    } else if (line < 2 * (int64_t)n) {
+        // ---- diagonal k of U (and its mirror) ----
+        const int k = (int)(line - n);
+        if (k >= wp) {
+            const int s_last = (n - 1 - k) / H;
+            uint32_t open = 0;
+            for (int s = 0; s <= s_last; ++s) {
+                const int64_t idx = strip_offset(s, n, wp, H) + (k - wp);
+                const uint32_t fb = j.dfirst[idx];
+                if (s < s_last && fb == (uint32_t)H) { open += H; continue; }
+                if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
+                open = s < s_last ? (uint32_t)j.dlast[idx] : 0u;
+            }
+        } else if (k == 0 && j.theiler == 0) {
+            // main diagonal: every cell (i,i) is recurrent (distance 0 <= eps)
+            emit(L.bd, kCapD, j.hd, (uint32_t)n, 1u, (uint32_t)n, j.flag);
+        }
+    }
+    __syncthreads();
+    const int hl = n + 1;
+    for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
+        if (t < kCapD && L.bd[t] && t < hl) atomicAdd(j.hd + t, (unsigned long long)L.bd[t]);
+        if (t < kCapV && L.bv[t] && t < hl) atomicAdd(j.hv + t, (unsigned long long)L.bv[t]);
+        if (L.bw[t] && t < hl) atomicAdd(j.hw + t, (unsigned long long)L.bw[t]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+using TileKernel = void (*)(const JobDesc *, const GroupDesc *, int, int *);
+
+template <int NORM>
+TileKernel pick_kernel(int m) {
+    switch (m) {
+        case 1: return k_tiles<NORM, 1>;
+        case 2: return k_tiles<NORM, 2>;
+        case 3: return k_tiles<NORM, 3>;
+        case 4: return k_tiles<NORM, 4>;
+        case 5: return k_tiles<NORM, 5>;
+        case 6: return k_tiles<NORM, 6>;
+        default: return k_tiles<NORM, 0>;
+    }
+}
+
+TileKernel tile_kernel(int norm, int m) {
+    if (norm == RQA_NORM_L1) return pick_kernel<RQA_NORM_L1>(m);
+    if (norm == RQA_NORM_L2) return pick_kernel<RQA_NORM_L2>(m);
+    return pick_kernel<RQA_NORM_LINF>(m);
+}
+
+int group_key(const KParams &kp) { return kp.norm * 16 + (kp.m <= kMaxM ? kp.m : 0); }
+
+struct Layout {
+    int H, nstrips;
+    int64_t entries;       // summary entries per array
+    int64_t tail_len;
+    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, bytes;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int default_waves(int64_t n) {
+    // Tall strips amortise the strip-edge summaries; short series use fewer waves
+    // per strip so that more strips are available.
+    if (n >= 16 * 1024 * 64) return 16;
+    if (n >= 4096 * 8) return 8;
+    return 4;
+}
+
+Layout layout_of(const Job &jb, int waves) {
+    Layout L{};
+    const int64_t n = jb.n_vec;
+    const int wp = jb.kp.theiler > 1 ? jb.kp.theiler : 1;
+    L.H = 64 * (waves > 0 ? waves : default_waves(n));
+    L.nstrips = n - wp > 0 ? (int)((n - wp + L.H - 1) / L.H) : 0;
+    // sum over strips of (n - wp - s H) entries
+    L.entries = (int64_t)L.nstrips * (n - wp) - (int64_t)L.H * ((int64_t)L.nstrips * (L.nstrips - 1) / 2);
+    if (L.entries < 1) L.entries = 1;
+    const int64_t c_last = (n - 1) / 64;
+    L.tail_len = 64 + (int64_t)(jb.kp.m - 1) * jb.kp.tau;
+    (void)c_last;
+    size_t off = 0;
+    L.off_tail = off; off += a256(sizeof(float) * (size_t)L.tail_len);
+    L.off_lead = off; off += a256(sizeof(uint32_t) * (size_t)n);
+    L.off_vf = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
+    L.off_vl = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
+    L.off_df = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
+    L.off_dl = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
+    L.bytes = off;
+    return L;
+}
+
+}  // namespace
+
+size_t engine_job_scratch_bytes(const Job &job, int waves) { return layout_of(job, waves).bytes; }
+
+size_t engine_launch_scratch_bytes(size_t njobs) {
+    return a256(sizeof(JobDesc) * njobs) + a256(sizeof(GroupDesc) * 64) + 256;
+}
+
+int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *staging,
+                  hipEvent_t staging_free, int waves, int groups_req, hipStream_t st) {
+    const int njobs = (int)jobs_in.size();
+    if (njobs == 0) return RQA_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RQA_EDEVICE;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return RQA_EDEVICE;
+
+    // Order: by (norm, m) group, then by decreasing size (largest strips first).
+    std::vector<int> order(njobs);
+    for (int k = 0; k < njobs; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ga = group_key(jobs_in[a].kp), gb = group_key(jobs_in[b].kp);
+        if (ga != gb) return ga < gb;
+        return jobs_in[a].n_vec > jobs_in[b].n_vec;
+    });
+
+    // Waves per workgroup: one value per launch (the workgroup size).
+    int w = waves;
+    if (w <= 0) {
+        int64_t nmax = 0;
+        for (const Job &jb : jobs_in) nmax = std::max<int64_t>(nmax, jb.n_vec);
+        w = default_waves(nmax);
+    }
+
+    // The previous launch that used `staging` must have consumed it.
+    if (staging_free && hipEventSynchronize(staging_free) != hipSuccess) return RQA_EDEVICE;
+
+    char *dbase = static_cast<char *>(launch_scratch);
+    JobDesc *hdesc = static_cast<JobDesc *>(staging);
+    GroupDesc *hgroups = reinterpret_cast<GroupDesc *>(static_cast<char *>(staging) +
+                                                       a256(sizeof(JobDesc) * njobs));
+    JobDesc *ddesc = reinterpret_cast<JobDesc *>(dbase);
+    GroupDesc *dgroups = reinterpret_cast<GroupDesc *>(dbase + a256(sizeof(JobDesc) * njobs));
+    int *dcounters = reinterpret_cast<int *>(dbase + a256(sizeof(JobDesc) * njobs) +
+                                             a256(sizeof(GroupDesc) * 64));
+
+    std::vector<int> gkeys;
+    int stitch_blocks = 0;
+    int ngroups = 0;
+    int strip_acc = 0;
+    for (int r = 0; r < njobs; ++r) {
+        const Job &jb = jobs_in[order[r]];
+        const KParams &kp = jb.kp;
+        const Layout lay = layout_of(jb, w);
+        const int key = group_key(kp);
+        if (ngroups == 0 || gkeys.back() != key) {
+            if (ngroups == 64) return RQA_EINVAL;
+            if (ngroups > 0) hgroups[ngroups - 1].items = strip_acc;
+            gkeys.push_back(key);
+            hgroups[ngroups] = GroupDesc{r, r + 1, 0, 0};
+            ++ngroups;
+            strip_acc = 0;
+        }
+        hgroups[ngroups - 1].job1 = r + 1;
+        char *scr = static_cast<char *>(jb.scratch);
+        JobDesc d{};
+        d.s = jb.series;
+        d.tail = reinterpret_cast<const float *>(scr + lay.off_tail);
+        d.hd = reinterpret_cast<unsigned long long *>(jb.hist);
+        d.hv = d.hd + (jb.n_vec + 1);
+        d.hw = d.hv + (jb.n_vec + 1);
+        d.flag = jb.flag;
+        d.lead = reinterpret_cast<uint32_t *>(scr + lay.off_lead);
+        d.vfirst = reinterpret_cast<uint16_t *>(scr + lay.off_vf);
+        d.vlast = reinterpret_cast<uint16_t *>(scr + lay.off_vl);
+        d.dfirst = reinterpret_cast<uint16_t *>(scr + lay.off_df);
+        d.dlast = reinterpret_cast<uint16_t *>(scr + lay.off_dl);
+        d.n_points = jb.n_points;
+        d.n = (int32_t)jb.n_vec;
+        d.m = kp.m;
+        d.tau = kp.tau;
+        d.norm = kp.norm;
+        d.theiler = kp.theiler;
+        d.wp = kp.theiler > 1 ? kp.theiler : 1;
+        d.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
+        d.H = lay.H;
+        d.nstrips = lay.nstrips;
+        d.c_last = (int32_t)((jb.n_vec - 1) / 64);
+        d.tail_len = (int32_t)lay.tail_len;
+        d.strip_base = strip_acc;
+        d.stitch_block0 = stitch_blocks;
+        strip_acc += lay.nstrips;
+        stitch_blocks += (int)((2 * jb.n_vec + kStitchThreads - 1) / kStitchThreads);
+        hdesc[r] = d;
+    }
+    hgroups[ngroups - 1].items = strip_acc;
+
+    const size_t desc_bytes = a256(sizeof(JobDesc) * njobs) + a256(sizeof(GroupDesc) * 64);
+    if (hipMemcpyAsync(dbase, staging, desc_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+        return RQA_EDEVICE;
+    if (staging_free && hipEventRecord(staging_free, st) != hipSuccess) return RQA_EDEVICE;
+
+    hipLaunchKernelGGL(k_reset, dim3((std::max(njobs, 64) + 255) / 256), dim3(256), 0, st, ddesc,
+                       njobs, dcounters, 64);
+    hipLaunchKernelGGL(k_prepare, dim3(64, njobs), dim3(256), 0, st, ddesc);
+
+    for (int g = 0; g < ngroups; ++g) {
+        const GroupDesc &gd = hgroups[g];
+        if (gd.items == 0) continue;
+        const KParams &kp = jobs_in[order[gd.job0]].kp;
+        TileKernel kern = tile_kernel(kp.norm, kp.m);
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, 0) != hipSuccess ||
+            occ < 1)
+            occ = 1;
+        int grid = groups_req > 0 ? groups_req : ncu * occ;
+        grid = std::min(grid, gd.items);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), 0, st, ddesc, dgroups, g, dcounters);
+    }
+    if (stitch_blocks > 0)
+        hipLaunchKernelGGL(k_stitch, dim3(stitch_blocks), dim3(kStitchThreads), 0, st, ddesc, njobs);
+    return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
+}
+
+}  // namespace rqa

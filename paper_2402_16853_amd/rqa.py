@@ -1,0 +1,292 @@
+"""Python binding of librqa (argument marshalling only; every step of the hot
+path runs in the HIP kernels of librqa.so).
+
+Mirrors the workflow of Sect. 7: parameters (Settings), a computation created
+from them, ``run`` on a series, and a result object with one member per
+measure.  PyTorch provides the device memory (CUDA/HIP float32 tensors) and the
+stream; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from ._lib import RqaMeasures, RqaParams, check, lib, EAGAIN, RQAError
+
+NORMS = {"l1": 1, "taxicab": 1, "manhattan": 1, "l2": 2, "euclidean": 2,
+         "linf": 3, "maximum": 3, "chebyshev": 3, 1: 1, 2: 2, 3: 3}
+
+MEASURE_FIELDS = ("rr", "det", "l", "lmax", "div", "l_entr", "lam", "tt", "vmax", "v_entr",
+                  "w", "wmax", "w_entr")
+
+
+def norm_code(norm) -> int:
+    key = norm.lower() if isinstance(norm, str) else norm
+    if key not in NORMS:
+        raise ValueError(f"unknown norm {norm!r}")
+    return NORMS[key]
+
+
+@dataclass
+class RQAResult:
+    """Measures (FP64) and the three line-length histograms (index = length)."""
+    measures: dict
+    diag: np.ndarray | None = None
+    vert: np.ndarray | None = None
+    white: np.ndarray | None = None
+    n_vec: int = 0
+    n_rec: int = 0
+    extra: dict = field(default_factory=dict)
+
+    # PyRQA-style attribute names (Tab. 3 of the paper)
+    @property
+    def recurrence_rate(self): return self.measures["rr"]
+    @property
+    def determinism(self): return self.measures["det"]
+    @property
+    def average_diagonal_line(self): return self.measures["l"]
+    @property
+    def longest_diagonal_line(self): return self.measures["lmax"]
+    @property
+    def divergence(self): return self.measures["div"]
+    @property
+    def entropy_diagonal_lines(self): return self.measures["l_entr"]
+    @property
+    def laminarity(self): return self.measures["lam"]
+    @property
+    def trapping_time(self): return self.measures["tt"]
+    @property
+    def longest_vertical_line(self): return self.measures["vmax"]
+    @property
+    def entropy_vertical_lines(self): return self.measures["v_entr"]
+    @property
+    def average_white_vertical_line(self): return self.measures["w"]
+    @property
+    def longest_white_vertical_line(self): return self.measures["wmax"]
+    @property
+    def entropy_white_vertical_lines(self): return self.measures["w_entr"]
+
+
+def _measures_dict(ms: RqaMeasures) -> dict:
+    d = {k: getattr(ms, k) for k in MEASURE_FIELDS}
+    d["n_rec"] = float(ms.n_rec)
+    d["n_vec"] = float(ms.n_vec)
+    return d
+
+
+def _device_series(series):
+    import torch
+    if not isinstance(series, torch.Tensor):
+        raise TypeError("series must be a torch tensor on the GPU")
+    if not series.is_cuda:
+        raise ValueError("series must live in device memory (a CUDA/HIP tensor)")
+    if series.dtype != torch.float32:
+        raise ValueError("series must be float32")
+    if series.dim() != 1 or not series.is_contiguous():
+        raise ValueError("series must be a contiguous 1-D tensor")
+    return series
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_params(m, tau, eps, norm, lmin=2, vmin=2, wmin=2, theiler=1) -> RqaParams:
+    return RqaParams(int(m), int(tau), float(np.float32(eps)), norm_code(norm), int(lmin),
+                     int(vmin), int(wmin), int(theiler))
+
+
+class RQA:
+    """One RQA computation (parameter set) bound to librqa's C ABI.
+
+    ``embedding_dimension``/``time_delay``/``radius``/``similarity_measure`` and
+    the minimum line lengths follow the Settings fields of Sect. 7.2; ``theiler``
+    is the Theiler window."""
+
+    def __init__(self, embedding_dimension, time_delay, radius, similarity_measure="euclidean",
+                 min_diagonal_line_length=2, min_vertical_line_length=2,
+                 min_white_vertical_line_length=2, theiler=1):
+        self.params = make_params(embedding_dimension, time_delay, radius, similarity_measure,
+                                  min_diagonal_line_length, min_vertical_line_length,
+                                  min_white_vertical_line_length, theiler)
+        h = ctypes.c_void_p()
+        p = self.params
+        check(lib().rqa_create(ctypes.byref(h), p.m, p.tau, p.eps, p.norm, p.lmin, p.vmin, p.wmin,
+                               p.theiler), "rqa_create")
+        self._h = h
+        self._keep = None
+        self._count = 0
+        self._nvec = []
+
+    @classmethod
+    def from_params(cls, p):
+        """From any object with fields m, tau, eps, norm, lmin, vmin, wmin, theiler."""
+        return cls(p.m, p.tau, p.eps, p.norm, p.lmin, p.vmin, p.wmin, p.theiler)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rqa_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hist_len(self, n_points: int) -> int:
+        out = ctypes.c_int64()
+        check(lib().rqa_hist_len(self._h, int(n_points), ctypes.byref(out)), "rqa_hist_len")
+        return out.value
+
+    def set_tiling(self, waves_per_group: int = 0, groups: int = 0):
+        check(lib().rqa_set_tiling(self._h, int(waves_per_group), int(groups)), "rqa_set_tiling")
+
+    def run(self, series, stream=None):
+        """Enqueue the RQA of a device series (asynchronous)."""
+        s = _device_series(series)
+        check(lib().rqa_run(self._h, ctypes.c_void_p(s.data_ptr()), s.numel(), _stream_ptr(stream)),
+              "rqa_run")
+        self._keep = s
+        self._count = 1
+        self._nvec = [self.hist_len(s.numel())]
+        return self
+
+    def result(self, histograms: bool = True) -> RQAResult:
+        return self._fetch(None, histograms)
+
+    def __call__(self, series, stream=None) -> RQAResult:
+        self.run(series, stream)
+        return self.result()
+
+    def run_batch(self, series, offsets, lengths, stream=None):
+        """Enqueue windows series[offsets[w]:offsets[w]+lengths[w]] in one launch."""
+        s = _device_series(series)
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        ln = np.ascontiguousarray(lengths, dtype=np.int64)
+        if off.shape != ln.shape or off.ndim != 1:
+            raise ValueError("offsets and lengths must be 1-D arrays of equal length")
+        check(lib().rqa_run_batch(self._h, ctypes.c_void_p(s.data_ptr()), s.numel(),
+                                  off.ctypes.data_as(ctypes.c_void_p),
+                                  ln.ctypes.data_as(ctypes.c_void_p), len(off),
+                                  _stream_ptr(stream)), "rqa_run_batch")
+        self._keep = s
+        self._count = len(off)
+        self._nvec = [int(L) - (self.params.m - 1) * self.params.tau for L in ln]
+        return self
+
+    def result_batch(self, index: int, histograms: bool = True) -> RQAResult:
+        return self._fetch(int(index), histograms)
+
+    def _fetch(self, index, histograms):
+        n = self._nvec[0 if index is None else index] if self._nvec else 0
+        ms = RqaMeasures()
+        if histograms and n > 0:
+            d = np.zeros(n + 1, dtype=np.uint64)
+            v = np.zeros(n + 1, dtype=np.uint64)
+            w = np.zeros(n + 1, dtype=np.uint64)
+            ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in (d, v, w)]
+        else:
+            d = v = w = None
+            ptrs = [None, None, None]
+        if index is None:
+            rc = lib().rqa_result(self._h, ctypes.byref(ms), *ptrs, n + 1)
+            check(rc, "rqa_result")
+        else:
+            rc = lib().rqa_result_batch(self._h, index, ctypes.byref(ms), *ptrs, n + 1)
+            check(rc, "rqa_result_batch")
+        return RQAResult(_measures_dict(ms), d, v, w, int(ms.n_vec), int(ms.n_rec))
+
+
+def measures_from_hist(diag, vert, white, params) -> dict:
+    """FP64 measures from host histograms through the library's own code."""
+    d = np.ascontiguousarray(diag, dtype=np.uint64)
+    v = np.ascontiguousarray(vert, dtype=np.uint64)
+    w = np.ascontiguousarray(white, dtype=np.uint64)
+    p = params if isinstance(params, RqaParams) else make_params(
+        params.m, params.tau, params.eps, params.norm, params.lmin, params.vmin, params.wmin,
+        params.theiler)
+    ms = RqaMeasures()
+    check(lib().rqa_measures_from_hist(d.ctypes.data_as(ctypes.c_void_p),
+                                       v.ctypes.data_as(ctypes.c_void_p),
+                                       w.ctypes.data_as(ctypes.c_void_p), len(d) - 1,
+                                       ctypes.byref(p), ctypes.byref(ms)), "rqa_measures_from_hist")
+    return _measures_dict(ms)
+
+
+class Server:
+    """Continuous-batching RQA server over librqa's serving API."""
+
+    def __init__(self, budget_bytes: int, streams: int = 4):
+        h = ctypes.c_void_p()
+        check(lib().rqa_server_create(ctypes.byref(h), int(budget_bytes), int(streams)),
+              "rqa_server_create")
+        self._h = h
+        self._jobs = {}
+
+    @staticmethod
+    def footprint(params, n_points: int) -> int:
+        p = params if isinstance(params, RqaParams) else make_params(
+            params.m, params.tau, params.eps, params.norm, params.lmin, params.vmin, params.wmin,
+            params.theiler)
+        out = ctypes.c_size_t()
+        check(lib().rqa_job_footprint(ctypes.byref(p), int(n_points), ctypes.byref(out)),
+              "rqa_job_footprint")
+        return out.value
+
+    def submit(self, params, series, stream=None) -> int:
+        s = _device_series(series)
+        p = params if isinstance(params, RqaParams) else make_params(
+            params.m, params.tau, params.eps, params.norm, params.lmin, params.vmin, params.wmin,
+            params.theiler)
+        t = ctypes.c_uint64()
+        check(lib().rqa_submit(self._h, ctypes.byref(p), ctypes.c_void_p(s.data_ptr()), s.numel(),
+                               _stream_ptr(stream), ctypes.byref(t)), "rqa_submit")
+        self._jobs[t.value] = (s, s.numel() - (p.m - 1) * p.tau)
+        return t.value
+
+    def _collect(self, fn, ticket, histograms):
+        if ticket not in self._jobs:
+            raise KeyError(ticket)
+        n = self._jobs[ticket][1]
+        ms = RqaMeasures()
+        if histograms:
+            arrs = [np.zeros(n + 1, dtype=np.uint64) for _ in range(3)]
+            ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
+        else:
+            arrs = [None] * 3
+            ptrs = [None] * 3
+        rc = fn(self._h, ctypes.c_uint64(ticket), ctypes.byref(ms), *ptrs, n + 1)
+        if rc == EAGAIN:
+            return None
+        del self._jobs[ticket]
+        check(rc, "rqa_poll/wait")
+        return RQAResult(_measures_dict(ms), *arrs, int(ms.n_vec), int(ms.n_rec))
+
+    def poll(self, ticket: int, histograms: bool = True):
+        """Result if the job is done, else None."""
+        return self._collect(lib().rqa_poll, ticket, histograms)
+
+    def wait(self, ticket: int, histograms: bool = True) -> RQAResult:
+        return self._collect(lib().rqa_wait, ticket, histograms)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().rqa_server_destroy(self._h)
+            self._h = None
+        self._jobs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["RQA", "RQAResult", "RQAError", "Server", "measures_from_hist", "make_params",
+           "norm_code"]

@@ -1,0 +1,118 @@
+"""HIP path vs the CPU oracle, element by element (GPU).
+
+Histograms must match bit-exactly; measures (FP64 from identical integers) within
+1e-12 relative.  Cases span several 64x64 tiles and strips with ragged tails,
+every norm, several m/tau, Theiler windows 0..large, and several workgroup
+shapes.  Each case prints its parameters before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+from workloads import Params, workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _announce(tag, **kw):
+    print(f"[case] {tag} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def assert_same(res, ref_hist, ref_meas, tag=""):
+    d0, v0, w0 = ref_hist
+    for name, a, b in (("diag", res.diag, d0), ("vert", res.vert, v0), ("white", res.white, w0)):
+        assert a.shape == b.shape, f"{tag} {name} length {a.shape} vs {b.shape}"
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0][:8]
+            raise AssertionError(f"{tag} {name} differs at lengths {bad.tolist()}: "
+                                 f"gpu {a[bad].tolist()} oracle {b[bad].tolist()}")
+    for k, ref in ref_meas.items():
+        got = res.measures[k]
+        if np.isnan(ref):
+            assert np.isnan(got), f"{tag} {k}: {got} vs NaN"
+        else:
+            assert abs(got - ref) <= TOL * max(1.0, abs(ref)), f"{tag} {k}: {got} vs {ref}"
+
+
+def run_gpu(series, p, cuda, waves=0, groups=0):
+    import torch
+    from paper_2402_16853_amd import RQA
+    comp = RQA.from_params(p)
+    if waves or groups:
+        comp.set_tiling(waves, groups)
+    res = comp(torch.from_numpy(np.ascontiguousarray(series, dtype=np.float32)).to(cuda))
+    comp.close()
+    return res
+
+
+def random_case(seed):
+    rng = np.random.default_rng(seed)
+    m = int(rng.integers(1, 8))
+    tau = int(rng.integers(1, 5))
+    n_vec = int(rng.choice([1, 2, 3, 63, 64, 65, 127, 128, 129, 200, 511, 777, 1024, 1100, 2100,
+                            3000]))
+    N = n_vec + (m - 1) * tau
+    kind = rng.integers(0, 3)
+    if kind == 0:
+        s = rng.random(N)
+    elif kind == 1:
+        s = np.cumsum(rng.normal(size=N)) * 0.1
+    else:
+        s = np.sin(np.arange(N) * 0.3) + 0.05 * rng.normal(size=N)
+    s = s.astype(np.float32)
+    norm = int(rng.integers(1, 4))
+    theiler = int(rng.choice([0, 1, 2, 5, 63, 64, 65, 300]))
+    eps = float(rng.uniform(0.05, 0.5))
+    return s, Params(m=m, tau=tau, eps=eps, norm=norm, lmin=int(rng.integers(1, 4)),
+                     vmin=int(rng.integers(1, 4)), wmin=int(rng.integers(1, 4)), theiler=theiler)
+
+
+@pytest.mark.parametrize("seed", list(range(40)))
+def test_random_small(seed, cuda, oracle_lib):
+    s, p = random_case(seed)
+    ref = oracle_lib.rqa(s, p)
+    for waves in (1, 4):
+        _announce("random", seed=seed, n=len(s), m=p.m, tau=p.tau, norm=p.norm, w=p.theiler,
+                  waves=waves)
+        res = run_gpu(s, p, cuda, waves=waves)
+        assert_same(res, *ref, tag=f"seed {seed} waves {waves}")
+
+
+@pytest.mark.parametrize("waves", [1, 2, 3, 8, 16])
+def test_tile_shapes(waves, cuda, oracle_lib):
+    """The result does not depend on the workgroup shape or count."""
+    s, p = workload("logistic", seed=3, n=3_333)
+    ref = oracle_lib.rqa(s, p)
+    for groups in (0, 1, 7):
+        _announce("shapes", waves=waves, groups=groups, n=len(s))
+        assert_same(run_gpu(s, p, cuda, waves=waves, groups=groups), *ref,
+                    tag=f"waves {waves} groups {groups}")
+
+
+def test_logistic_config(cuda, oracle_lib):
+    """Logistic map r=3.9, N=2,000, m=2, tau=1, L2, eps=0.1."""
+    for seed in range(3):
+        s, p = workload("logistic", seed=seed)
+        _announce("logistic", seed=seed)
+        assert_same(run_gpu(s, p, cuda), *oracle_lib.rqa(s, p), tag=f"logistic {seed}")
+
+
+def test_constant_and_periodic(cuda, oracle_lib):
+    for theiler in (0, 1, 3):
+        s = np.full(1500, 0.25, dtype=np.float32)
+        p = Params(m=2, tau=3, eps=0.0, norm=3, theiler=theiler)
+        _announce("constant", theiler=theiler)
+        assert_same(run_gpu(s, p, cuda), *oracle_lib.rqa(s, p), tag=f"constant w={theiler}")
+    s = (np.arange(2000) % 7).astype(np.float32)
+    p = Params(m=3, tau=2, eps=0.5, norm=2, theiler=1)
+    _announce("periodic")
+    assert_same(run_gpu(s, p, cuda, waves=2), *oracle_lib.rqa(s, p), tag="periodic")
+
+
+def test_ar1_config(cuda, oracle_lib):
+    """AR(1)+seasonal, N=100,000, m=3, tau=6, L2, eps=0.5 (full size)."""
+    s, p = workload("ar1_season", seed=0)
+    ref = oracle_lib.rqa(s, p)
+    _announce("ar1_season", n=len(s))
+    assert_same(run_gpu(s, p, cuda), *ref, tag="ar1_season")
