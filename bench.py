@@ -1,0 +1,278 @@
+"""Benchmark of the RQA hot path on one MI355X.
+
+Headline: full RQA (validation, fused predicate + line detection, stitch/join,
+histogram read-back and FP64 measures) of the Lorenz-63 x-coordinate,
+N = 1,048,576 points, m=3, tau=10, L-infinity, eps = 0.05 std, lmin=vmin=wmin=2,
+Theiler window 1.  value = n_vec^2 recurrence-matrix cells per second (Gcells/s)
+with the series already resident in device memory.
+
+Also reported (outside the timed K steps):
+  roofline      live hipEvent time of the fused tile kernel vs the FP32 VALU peak
+  cpu_baseline  the CPU oracle on a bounded sample of the same series
+  batched       400 uneven sliding windows of uniform noise in one launch, vs the
+                same windows run one by one
+  served        a Poisson stream (200 req/s) of mixed jobs through the
+                continuous-batching server: p50/p99 latency and Gcells/s, vs the
+                same jobs run one by one
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+REPO = os.path.dirname(os.path.abspath(__file__))
+if REPO not in sys.path:
+    sys.path.insert(0, REPO)
+
+METRIC = "recurrence cells/s (Gcells/s) full RQA @N=1M, 1 GPU; batched p50/p99 latency"
+
+# FP32 VALU peak without FMA and without packed math: 256 CUs x 64 lanes x 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def ops_per_pair(m: int, norm: int) -> int:
+    """Algorithmic FP32 operations of one predicate evaluation: m subtractions,
+    m-1 accumulations (add or max), m squarings for L2, one comparison."""
+    return 3 * m if norm == 2 else 2 * m
+
+
+def unique_pairs(n: int, theiler: int) -> int:
+    """Pairs i < j with j - i >= max(theiler, 1)."""
+    w = max(theiler, 1)
+    k = n - w
+    return k * (k + 1) // 2 if k > 0 else 0
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def bench_headline(args, torch, RQA, workload):
+    s, p = workload("lorenz", seed=args.seed)
+    n = len(s) - (p.m - 1) * p.tau
+    dev = torch.device("cuda:0")
+    ds = torch.from_numpy(s).to(dev)
+    comp = RQA.from_params(p)
+    comp.set_profiling(True)
+    log(f"[bench] lorenz N={len(s)} n_vec={n} eps={p.eps:.6g}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        comp.run(ds)
+        comp.result(histograms=True)
+    tiles, stitch, prep = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        comp.run(ds)
+        res = comp.result(histograms=True)
+        tm = comp.timings()
+        tiles.append(tm["tiles_ms"])
+        stitch.append(tm["stitch_ms"])
+        prep.append(tm["prepare_ms"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    cells = float(n) * float(n)
+    gcells = cells / (ms * 1e-3) / 1e9
+    tile_ms = float(np.mean(tiles))
+    ops = unique_pairs(n, p.theiler) * ops_per_pair(p.m, p.norm)
+    achieved = ops / (tile_ms * 1e-3) / 1e12
+    log(f"[bench] {ms:.2f} ms/step  tiles {tile_ms:.2f} ms  stitch {np.mean(stitch):.2f} ms  "
+        f"prepare {np.mean(prep):.2f} ms  RR={res.measures['rr']:.6f} DET={res.measures['det']:.6f}")
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+            "kernel": "k_tiles<Linf,m=3>", "kernel_ms": round(tile_ms, 3),
+            "ops_per_launch": ops,
+            "stitch_ms": round(float(np.mean(stitch)), 3),
+            "prepare_ms": round(float(np.mean(prep)), 3)}
+    out = {"ms": ms, "gcells": gcells, "n": n, "p": p, "roof": roof, "series": s,
+           "measures": res.measures}
+    comp.close()
+    del ds
+    return out
+
+
+def bench_cpu_baseline(args, hl):
+    import oracle
+    threads = os.cpu_count() or 1
+    s = hl["series"][: args.cpu_points]
+    p = hl["p"]
+    n = len(s) - (p.m - 1) * p.tau
+    log(f"[bench] cpu oracle sample: first {len(s)} points ({threads} threads)")
+    t0 = time.perf_counter()
+    oracle.histograms(s, p.m, p.tau, p.eps, p.norm, p.theiler, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(float(n) * n / dt / 1e9, 4), "unit": "Gcells/s", "cores": threads,
+            "kind": "oracle", "seconds": round(dt, 2),
+            "sample": f"first {len(s)} points of the same Lorenz series (n_vec={n}), "
+                      f"full matrix, {threads} threads, {cpu_model()}"}
+
+
+def bench_batched(args, torch, RQA, workload, windows_plan):
+    s, p = workload("uniform", seed=args.seed)
+    off, ln = windows_plan(len(s), 400, 1000, 20000, seed=args.seed)
+    dev = torch.device("cuda:0")
+    ds = torch.from_numpy(s).to(dev)
+    comp = RQA.from_params(p)
+    nv = ln - (p.m - 1) * p.tau
+    cells = float(np.sum(nv.astype(np.float64) ** 2))
+    log(f"[bench] batched: {len(off)} windows, {cells:.3e} cells")
+    for _ in range(2):
+        comp.run_batch(ds, off, ln)
+        for w in range(len(off)):
+            comp.result_batch(w, histograms=False)
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        comp.run_batch(ds, off, ln)
+        for w in range(len(off)):
+            comp.result_batch(w, histograms=False)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    # the same windows, one launch each
+    single = RQA.from_params(p)
+    views = [ds[int(o):int(o) + int(L)] for o, L in zip(off, ln)]
+    for v in views[:8]:
+        single.run(v)
+        single.result(histograms=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in views:
+        single.run(v)
+        single.result(histograms=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    comp.close()
+    single.close()
+    return {"windows": int(len(off)), "cells": cells, "ms": round(tb * 1e3, 3),
+            "gcells_per_s": round(cells / tb / 1e9, 3),
+            "sequential_ms": round(ts * 1e3, 3),
+            "sequential_gcells_per_s": round(cells / ts / 1e9, 3),
+            "speedup_vs_sequential": round(ts / tb, 3)}
+
+
+def bench_served(args, torch, RQA, Server, served_requests):
+    reqs = served_requests(args.requests, rate_hz=200.0, seed=args.seed)
+    dev = torch.device("cuda:0")
+    dser = [torch.from_numpy(r.series).to(dev) for r in reqs]
+    torch.cuda.synchronize()
+    cells = float(sum((len(r.series) - (r.params.m - 1) * r.params.tau) ** 2 for r in reqs))
+    budget = 16 << 30
+    srv = Server(budget, streams=4)
+    log(f"[bench] served: {len(reqs)} requests over {reqs[-1].arrival:.2f} s, {cells:.3e} cells")
+    # warm-up: a few jobs
+    for r, d in list(zip(reqs, dser))[:4]:
+        srv.wait(srv.submit(r.params, d), histograms=False)
+    lat = []
+    pending = {}
+    t_start = time.perf_counter()
+    i = 0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t_start
+        while i < len(reqs) and reqs[i].arrival <= now:
+            t_sub = time.perf_counter()
+            pending[srv.submit(reqs[i].params, dser[i])] = t_sub
+            i += 1
+        done = []
+        for t, t_sub in pending.items():
+            if srv.poll(t, histograms=False) is not None:
+                lat.append(time.perf_counter() - t_sub)
+                done.append(t)
+        for t in done:
+            del pending[t]
+        if not done:
+            time.sleep(0.0002)
+    span = time.perf_counter() - t_start
+    srv.close()
+    # the same jobs, one at a time
+    t0 = time.perf_counter()
+    for r, d in zip(reqs, dser):
+        c = RQA.from_params(r.params)
+        c.run(d)
+        c.result(histograms=False)
+        c.close()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    lat_ms = np.array(lat) * 1e3
+    return {"requests": len(reqs), "rate_hz": 200.0, "cells": cells,
+            "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+            "span_s": round(span, 3), "gcells_per_s": round(cells / span / 1e9, 3),
+            "sequential_busy_s": round(ts, 3),
+            "sequential_gcells_per_s": round(cells / ts / 1e9, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-points", type=int, default=120_000)
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the RQA engine here is single-GPU); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2402_16853_amd import RQA, Server
+    from workloads import workload, windows_plan, served_requests
+
+    hl = bench_headline(args, torch, RQA, workload)
+    extra = {}
+    if not args.quick and not args.no_batched:
+        extra["batched"] = bench_batched(args, torch, RQA, workload, windows_plan)
+    if not args.quick and not args.no_served:
+        extra["served"] = bench_served(args, torch, RQA, Server, served_requests)
+    cpu = None
+    if not args.quick and not args.no_cpu:
+        cpu = bench_cpu_baseline(args, hl)
+
+    p = hl["p"]
+    line = {
+        "metric": METRIC, "value": round(hl["gcells"], 3), "unit": "Gcells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(hl["ms"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "lorenz63_x_N1048576_m3_tau10_linf_eps0.05std_w1",
+                   "n_points": len(hl["series"]), "n_vec": hl["n"], "m": p.m, "tau": p.tau,
+                   "norm": "Linf", "eps": p.eps, "lmin": p.lmin, "vmin": p.vmin, "wmin": p.wmin,
+                   "theiler": p.theiler, "seed": args.seed},
+        "roofline": hl["roof"],
+        "cpu_baseline": cpu,
+        "measures": {k: (None if not np.isfinite(v) else round(float(v), 9))
+                     for k, v in hl["measures"].items()},
+    }
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -140,6 +140,15 @@ int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert,
  * launch (0 = one per compute unit).  Results never depend on these. */
 int rqa_set_tiling(rqa_handle *h, int32_t waves_per_group, int32_t groups);
 
+/* Phase timing (hipEvents recorded on the run's stream).  With profiling on,
+ * each rqa_run / rqa_run_batch records events around its three phases; after
+ * the run, rqa_get_timings waits for it and returns the milliseconds spent in
+ * preparation (validation, zeroing), in the fused tile kernel (operators I-III,
+ * Sect. 4.2) and in the stitch/join kernel (recombination, Sect. 4.1).  Any
+ * output pointer may be NULL.  RQA_ESTATE if the last run was not profiled. */
+int rqa_set_profiling(rqa_handle *h, int32_t enable);
+int rqa_get_timings(rqa_handle *h, double *prepare_ms, double *tiles_ms, double *stitch_ms);
+
 /* Release the handle and its device workspace (waits for outstanding work). */
 void rqa_destroy(rqa_handle *h);
 

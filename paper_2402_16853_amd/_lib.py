@@ -48,6 +48,10 @@ SIGNATURES = {
     "rqa_measures_from_hist": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(RqaParams),
                                               ctypes.POINTER(RqaMeasures)]),
     "rqa_set_tiling": (ctypes.c_int, [_P, _I32, _I32]),
+    "rqa_set_profiling": (ctypes.c_int, [_P, _I32]),
+    "rqa_get_timings": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
     "rqa_destroy": (None, [_P]),
     "rqa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "rqa_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, _I32]),

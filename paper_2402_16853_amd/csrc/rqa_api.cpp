@@ -72,6 +72,9 @@ struct rqa_handle {
     void *staging = nullptr;        // pinned host buffer for launch descriptors
     size_t staging_bytes = 0;
     hipEvent_t staging_free = nullptr;   // recorded when a launch has read `staging`
+    bool profiling = false;
+    bool prof_valid = false;
+    PhaseEvents prof{};
     int waves = 0;                  // 0 = default tiling
     int groups = 0;                 // 0 = one workgroup per compute unit
     bool has_run = false;
@@ -139,7 +142,13 @@ int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_
         jb.scratch = p + hb + kFlagBytes;
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    rc = engine_launch(jobs, base, h->staging, h->staging_free, h->waves, h->groups, st);
+    if (h->profiling && !h->prof.ev[0]) {
+        for (hipEvent_t &e : h->prof.ev)
+            if (hipEventCreate(&e) != hipSuccess) return RQA_EDEVICE;
+    }
+    rc = engine_launch(jobs, base, h->staging, h->staging_free, h->waves, h->groups, st,
+                       h->profiling ? &h->prof : nullptr);
+    h->prof_valid = h->profiling && rc == RQA_OK;
     if (rc != RQA_OK) return rc;
     h->nvec = std::move(nvec);
     h->job_off = std::move(off);
@@ -240,11 +249,35 @@ int rqa_set_tiling(rqa_handle *h, int32_t waves_per_group, int32_t groups) {
     return RQA_OK;
 }
 
+int rqa_set_profiling(rqa_handle *h, int32_t enable) {
+    if (!h) return RQA_EINVAL;
+    h->profiling = enable != 0;
+    h->prof_valid = false;
+    return RQA_OK;
+}
+
+int rqa_get_timings(rqa_handle *h, double *prepare_ms, double *tiles_ms, double *stitch_ms) {
+    if (!h) return RQA_EINVAL;
+    if (!h->prof_valid) return RQA_ESTATE;
+    if (hipEventSynchronize(h->prof.ev[3]) != hipSuccess) return RQA_EDEVICE;
+    float a = 0.f, b = 0.f, c = 0.f;
+    if (hipEventElapsedTime(&a, h->prof.ev[0], h->prof.ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&b, h->prof.ev[1], h->prof.ev[2]) != hipSuccess ||
+        hipEventElapsedTime(&c, h->prof.ev[2], h->prof.ev[3]) != hipSuccess)
+        return RQA_EDEVICE;
+    if (prepare_ms) *prepare_ms = a;
+    if (tiles_ms) *tiles_ms = b;
+    if (stitch_ms) *stitch_ms = c;
+    return RQA_OK;
+}
+
 void rqa_destroy(rqa_handle *h) {
     if (!h) return;
     if (h->has_run) hipStreamSynchronize(h->stream);
     if (h->staging) hipHostFree(h->staging);
     if (h->staging_free) hipEventDestroy(h->staging_free);
+    for (hipEvent_t e : h->prof.ev)
+        if (e) hipEventDestroy(e);
     delete h;
 }
 

@@ -55,8 +55,15 @@ size_t engine_launch_scratch_bytes(size_t njobs);
 // `staging` is pinned host memory of the same size; `staging_free` (may be
 // null) is an event the engine waits on before rewriting `staging` and records
 // once the launch has consumed it.  waves = 0 / groups = 0 pick defaults.
+// Optional phase events recorded on the launch stream: [0] before preparation,
+// [1] before the tile kernel(s), [2] after them, [3] after the stitch kernel.
+struct PhaseEvents {
+    hipEvent_t ev[4];
+};
+
 int engine_launch(const std::vector<Job> &jobs, void *launch_scratch, void *staging,
-                  hipEvent_t staging_free, int waves, int groups, hipStream_t stream);
+                  hipEvent_t staging_free, int waves, int groups, hipStream_t stream,
+                  const PhaseEvents *phases = nullptr);
 
 // Host FP64 measures from histograms of length n+1.
 void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,

@@ -508,6 +508,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                 const int klo = kup - 64;               // diagonal of the lower part
                 Run up;
                 if (wave == 0) up = Run{(uint32_t)(D & 1ull), 0u, 1u};
+                else if (jbase + q > n - 1) up = Run{0u, 0u, 0u};   // starts past the border
                 else up = unpack_run(L.dslot[(step - 1) & 1][wave - 1][lane]);
                 {
                     const bool ok = kup >= wp && kup <= n - 1 - R0;
@@ -519,9 +520,14 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                     const bool ok = klo >= wp && klo <= n - 1 - R0;
                     LineCtx lc{&j, bins, soff + (klo - wp), ok, 0u};
                     run_segment<kDiag>(D, (uint32_t)(64 - q), 64u, lw, lc);
-                    if (wave < nw - 1) {
+                    // The lower part ends on row R+63.  Diagonals with no cell on
+                    // the next row end here at the right border; the others go to
+                    // the wave below or, from the last wave, into the summary.
+                    if (R + 64 + klo > n - 1) {
+                        if (lw.color || lw.first) finish_run<kDiag>(lc, lw.color, lw.len, lw.first);
+                    } else if (wave < nw - 1) {
                         L.dslot[step & 1][wave][lane] = pack_run(lw);
-                    } else if (ok && R0 + H + klo <= n - 1) {
+                    } else if (ok) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
                         j.dlast[soff + (klo - wp)] = b;
                         if (lw.first) j.dfirst[soff + (klo - wp)] = b;
@@ -759,7 +765,8 @@ size_t engine_launch_scratch_bytes(size_t njobs) {
 }
 
 int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *staging,
-                  hipEvent_t staging_free, int waves, int groups_req, hipStream_t st) {
+                  hipEvent_t staging_free, int waves, int groups_req, hipStream_t st,
+                  const PhaseEvents *phases) {
     const int njobs = (int)jobs_in.size();
     if (njobs == 0) return RQA_OK;
     int dev = 0;
@@ -853,10 +860,12 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         return RQA_EDEVICE;
     if (staging_free && hipEventRecord(staging_free, st) != hipSuccess) return RQA_EDEVICE;
 
+    if (phases) hipEventRecord(phases->ev[0], st);
     hipLaunchKernelGGL(k_reset, dim3((std::max(njobs, 64) + 255) / 256), dim3(256), 0, st, ddesc,
                        njobs, dcounters, 64);
     hipLaunchKernelGGL(k_prepare, dim3(64, njobs), dim3(256), 0, st, ddesc);
 
+    if (phases) hipEventRecord(phases->ev[1], st);
     for (int g = 0; g < ngroups; ++g) {
         const GroupDesc &gd = hgroups[g];
         if (gd.items == 0) continue;
@@ -870,8 +879,10 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         grid = std::min(grid, gd.items);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), 0, st, ddesc, dgroups, g, dcounters);
     }
+    if (phases) hipEventRecord(phases->ev[2], st);
     if (stitch_blocks > 0)
         hipLaunchKernelGGL(k_stitch, dim3(stitch_blocks), dim3(kStitchThreads), 0, st, ddesc, njobs);
+    if (phases) hipEventRecord(phases->ev[3], st);
     return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
 }
 

@@ -144,6 +144,16 @@ class RQA:
         check(lib().rqa_hist_len(self._h, int(n_points), ctypes.byref(out)), "rqa_hist_len")
         return out.value
 
+    def set_profiling(self, enable: bool = True):
+        check(lib().rqa_set_profiling(self._h, 1 if enable else 0), "rqa_set_profiling")
+
+    def timings(self) -> dict:
+        """Milliseconds of the last profiled run: prepare, tiles, stitch."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(lib().rqa_get_timings(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+              "rqa_get_timings")
+        return {"prepare_ms": a.value, "tiles_ms": b.value, "stitch_ms": c.value}
+
     def set_tiling(self, waves_per_group: int = 0, groups: int = 0):
         check(lib().rqa_set_tiling(self._h, int(waves_per_group), int(groups)), "rqa_set_tiling")
 
@@ -154,7 +164,7 @@ class RQA:
               "rqa_run")
         self._keep = s
         self._count = 1
-        self._nvec = [self.hist_len(s.numel())]
+        self._nvec = [self.hist_len(s.numel()) - 1]
         return self
 
     def result(self, histograms: bool = True) -> RQAResult:
