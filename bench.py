@@ -72,6 +72,19 @@ def bench_headline(args, torch, RQA, workload):
     ds = torch.from_numpy(s).to(dev)
     comp = RQA.from_params(p)
     comp.set_profiling(True)
+    if args.sweep:
+        for w in (4, 8, 16):
+            comp.set_tiling(w, 0)
+            comp.run(ds)
+            comp.result(histograms=False)
+            t = []
+            for _ in range(2):
+                comp.run(ds)
+                comp.result(histograms=False)
+                t.append(comp.timings())
+            log(f"[sweep] waves={w} tiles {np.mean([x['tiles_ms'] for x in t]):.2f} ms "
+                f"stitch {np.mean([x['stitch_ms'] for x in t]):.2f} ms")
+    comp.set_tiling(args.waves, 0)
     log(f"[bench] lorenz N={len(s)} n_vec={n} eps={p.eps:.6g}; warmup {args.warmup}")
     for _ in range(args.warmup):
         comp.run(ds)
@@ -232,6 +245,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = default)")
+    ap.add_argument("--sweep", action="store_true", help="time the tile kernel per waves setting")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the RQA engine here is single-GPU); "

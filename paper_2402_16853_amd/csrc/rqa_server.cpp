@@ -4,13 +4,16 @@
 // * The server owns one device pool of `budget` bytes, carved up by a
 //   first-fit allocator; a job is admitted (FIFO) when its footprint fits, so
 //   no hipMalloc happens on the request path.
-// * A worker thread groups all jobs admitted since the last launch into one
+// * A worker thread groups all jobs admitted since its last launch into one
 //   batched launch of the engine on the next stream of a small pool; jobs that
 //   arrive while earlier launches run are launched on another stream and
 //   overlap with them on the device.
-// * Each launch copies its histograms into pinned host buffers and then fires a
-//   host callback that marks its jobs done and returns their device memory to
-//   the pool; the worker then admits more jobs.
+// * Each launch copies its histograms into pinned host buffers (recycled
+//   through a cache) and then fires a host callback that marks its jobs done
+//   and returns their device memory to the pool; the worker then admits more.
+// * No HIP call is made while the server mutex is held: host callbacks take the
+//   mutex, and a HIP call that waits on a stream could otherwise wait for a
+//   callback that waits for the mutex.
 // Results are integer histograms, so a job's result does not depend on what
 // else runs beside it.
 #include <hip/hip_runtime.h>
@@ -34,7 +37,7 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// First-fit allocator over [0, size) with coalescing free list.
+// First-fit allocator over [0, size) with a coalescing free list.
 class Pool {
 public:
     void reset(size_t size) {
@@ -87,11 +90,13 @@ struct ServedJob {
     size_t off = 0;
     hipEvent_t ready = nullptr;    // recorded on the caller's stream at submit
     uint64_t *host = nullptr;      // pinned: 3*(n+1) histograms + flag word
+    size_t host_bytes = 0;
     int state = kQueued;
     int rc = RQA_OK;
 };
 
-struct Launch;
+constexpr size_t kMaxBatch = 256;
+constexpr size_t kFlagBytes = 256;
 
 }  // namespace
 
@@ -110,8 +115,10 @@ struct rqa_server {
     size_t next_stream = 0;
     std::deque<ServedJob *> pending;
     std::unordered_map<uint64_t, ServedJob *> jobs;
+    std::multimap<size_t, void *> pinned_free;   // recycled pinned result buffers
     uint64_t next_ticket = 1;
     int inflight = 0;
+    uint64_t completions = 0;   // launches finished so far
     bool stop = false;
     std::thread worker;
 };
@@ -127,15 +134,22 @@ size_t job_hist_bytes(int64_t n_vec) {
     return align256(sizeof(uint64_t) * 3 * static_cast<size_t>(n_vec + 1));
 }
 
-constexpr size_t kMaxBatch = 256;
-constexpr size_t kFlagBytes = 256;
-
 size_t job_scratch_bytes(const rqa_params &p, int64_t n_points, int64_t n_vec) {
     Job one;
     one.n_points = n_points;
     one.n_vec = n_vec;
     one.kp = make_kparams(p);
     return align256(engine_job_scratch_bytes(one, 0));
+}
+
+// Pinned buffer of at least `bytes` from the cache (lock held), or nullptr.
+void *take_pinned(rqa_server *srv, size_t bytes, size_t *got) {
+    auto it = srv->pinned_free.lower_bound(bytes);
+    if (it == srv->pinned_free.end()) return nullptr;
+    void *p = it->second;
+    *got = it->first;
+    srv->pinned_free.erase(it);
+    return p;
 }
 
 void on_launch_done(void *arg) {
@@ -150,34 +164,39 @@ void on_launch_done(void *arg) {
             srv->pool.release(j->off, j->footprint);
         }
         --srv->inflight;
+        ++srv->completions;
     }
     srv->cv.notify_all();
     srv->done_cv.notify_all();
     delete ln;
 }
 
-// Launch every admissible queued job (FIFO, stop at the first that does not
-// fit).  Called with the lock held; HIP calls are made with it held, which is
-// fine because callbacks never call into HIP.
-void admit_and_launch(rqa_server *srv) {
+// Launch every admissible queued job (FIFO, stopping at the first that does
+// not fit) as one batched launch.  Entered and left with `lk` held; the HIP
+// calls run with it released.  Returns the number of jobs launched.
+size_t admit_and_launch(rqa_server *srv, std::unique_lock<std::mutex> &lk) {
     std::vector<ServedJob *> batch;
     while (!srv->pending.empty() && batch.size() < kMaxBatch) {
         ServedJob *j = srv->pending.front();
         size_t off = 0;
         if (!srv->pool.alloc(j->footprint, &off)) break;
         j->off = off;
+        j->state = kRunning;
         srv->pending.pop_front();
         batch.push_back(j);
     }
-    if (batch.empty()) return;
+    if (batch.empty()) return 0;
     const size_t slot = srv->next_stream;
-    hipStream_t st = srv->streams[slot];
     srv->next_stream = (srv->next_stream + 1) % srv->streams.size();
+    ++srv->inflight;
+    lk.unlock();
 
+    hipStream_t st = srv->streams[slot];
     std::vector<Job> ej;
     ej.reserve(batch.size());
+    int rc = RQA_OK;
     for (ServedJob *j : batch) {
-        hipStreamWaitEvent(st, j->ready, 0);
+        if (hipStreamWaitEvent(st, j->ready, 0) != hipSuccess) rc = RQA_EDEVICE;
         char *base = srv->pool_base + j->off;
         Job e;
         e.series = j->series;
@@ -188,9 +207,9 @@ void admit_and_launch(rqa_server *srv) {
         e.scratch = base + j->hist_bytes + kFlagBytes;
         e.kp = make_kparams(j->p);
         ej.push_back(e);
-        j->state = kRunning;
     }
-    int rc = engine_launch(ej, srv->launch_scratch[slot], srv->staging[slot],
+    if (rc == RQA_OK)
+        rc = engine_launch(ej, srv->launch_scratch[slot], srv->staging[slot],
                            srv->staging_free[slot], 0, 0, st);
     for (size_t k = 0; k < batch.size() && rc == RQA_OK; ++k) {
         ServedJob *j = batch[k];
@@ -202,18 +221,22 @@ void admit_and_launch(rqa_server *srv) {
     }
     Launch *ln = new Launch{srv, batch};
     if (rc == RQA_OK && hipLaunchHostFunc(st, on_launch_done, ln) == hipSuccess) {
-        ++srv->inflight;
-        return;
+        lk.lock();
+        return batch.size();
     }
-    // Launch failed: fail the jobs and wait for the stream before releasing.
+    // The launch failed: wait for the stream, then fail the jobs.
     hipStreamSynchronize(st);
+    delete ln;
+    lk.lock();
     for (ServedJob *j : batch) {
         j->state = kFailed;
         j->rc = rc == RQA_OK ? RQA_EDEVICE : rc;
         srv->pool.release(j->off, j->footprint);
     }
-    delete ln;
+    --srv->inflight;
+    ++srv->completions;
     srv->done_cv.notify_all();
+    return batch.size();
 }
 
 void worker_main(rqa_server *srv) {
@@ -223,28 +246,32 @@ void worker_main(rqa_server *srv) {
         srv->cv.wait(lk, [srv] { return srv->stop || !srv->pending.empty(); });
         if (srv->stop && srv->pending.empty()) break;
         const size_t before = srv->pending.size();
-        admit_and_launch(srv);
-        if (srv->pending.size() == before) {
-            // Nothing fit: wait for a completion (or a stop request).
-            srv->cv.wait(lk, [srv, before] {
-                return srv->stop || srv->inflight == 0 || srv->pending.size() != before;
-            });
-            if (srv->inflight == 0 && srv->pending.size() == before && !srv->stop) {
-                // Head job cannot fit even in an empty pool (guarded at submit).
-                ServedJob *j = srv->pending.front();
-                srv->pending.pop_front();
-                j->state = kFailed;
-                j->rc = RQA_EBUDGET;
-                srv->done_cv.notify_all();
-            }
+        const uint64_t seen = srv->completions;
+        if (admit_and_launch(srv, lk) > 0) continue;
+        if (srv->inflight == 0) {
+            // Nothing runs, so the whole pool is free, and still the head job does
+            // not fit (cannot happen for jobs accepted by rqa_submit).
+            ServedJob *j = srv->pending.front();
+            srv->pending.pop_front();
+            j->state = kFailed;
+            j->rc = RQA_EBUDGET;
+            srv->done_cv.notify_all();
+            continue;
         }
+        // Wait until a launch completes (returning memory to the pool), new jobs
+        // arrive, or a stop is requested.
+        srv->cv.wait(lk, [srv, before, seen] {
+            return srv->stop || srv->completions != seen || srv->pending.size() != before;
+        });
     }
 }
 
+// Copy a finished job's results out and retire it (lock held; no HIP calls).
+// Hands back the job's event, to be destroyed once the lock is released.
 int collect(rqa_server *srv, ServedJob *j, rqa_measures *out, uint64_t *diag, uint64_t *vert,
-            uint64_t *white) {
+            uint64_t *white, hipEvent_t *ev_out) {
     const int64_t n = j->n_vec;
-    int rc = j->rc;
+    const int rc = j->rc;
     if (rc == RQA_OK) {
         const uint64_t *hd = j->host, *hv = hd + (n + 1), *hw = hv + (n + 1);
         if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * (n + 1));
@@ -253,8 +280,8 @@ int collect(rqa_server *srv, ServedJob *j, rqa_measures *out, uint64_t *diag, ui
         if (out) measures_from_hist(hd, hv, hw, n, j->p, out);
     }
     srv->jobs.erase(j->ticket);
-    hipHostFree(j->host);
-    hipEventDestroy(j->ready);
+    srv->pinned_free.emplace(j->host_bytes, j->host);
+    *ev_out = j->ready;
     delete j;
     return rc;
 }
@@ -331,17 +358,27 @@ int rqa_submit(rqa_server *srv, const rqa_params *p, const float *d_series, int6
     j->n_vec = n_points - static_cast<int64_t>(p->m - 1) * p->tau;
     j->footprint = fp;
     j->hist_bytes = job_hist_bytes(j->n_vec);
-    if (hipHostMalloc(reinterpret_cast<void **>(&j->host),
-                      sizeof(uint64_t) * (3 * static_cast<size_t>(j->n_vec + 1) + 1),
-                      hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        delete j;
-        return RQA_ENOMEM;
+    const size_t need = sizeof(uint64_t) * (3 * static_cast<size_t>(j->n_vec + 1) + 1);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        j->host = static_cast<uint64_t *>(take_pinned(srv, need, &j->host_bytes));
     }
-    std::memset(j->host, 0, sizeof(uint64_t) * (3 * static_cast<size_t>(j->n_vec + 1) + 1));
+    if (!j->host) {
+        size_t cap = 4096;
+        while (cap < need) cap <<= 1;
+        if (hipHostMalloc(reinterpret_cast<void **>(&j->host), cap, hipHostMallocDefault) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            delete j;
+            return RQA_ENOMEM;
+        }
+        j->host_bytes = cap;
+    }
+    j->host[3 * (j->n_vec + 1)] = 0;
     if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(j->ready, static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
-        hipHostFree(j->host);
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->pinned_free.emplace(j->host_bytes, j->host);
         delete j;
         return RQA_EDEVICE;
     }
@@ -359,25 +396,37 @@ int rqa_submit(rqa_server *srv, const rqa_params *p, const float *d_series, int6
 int rqa_poll(rqa_server *srv, uint64_t ticket, rqa_measures *out, uint64_t *diag, uint64_t *vert,
              uint64_t *white, int64_t hist_len) {
     if (!srv) return RQA_EINVAL;
-    std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->jobs.find(ticket);
-    if (it == srv->jobs.end()) return RQA_ENOTFOUND;
-    ServedJob *j = it->second;
-    if ((diag || vert || white) && hist_len < j->n_vec + 1) return RQA_ESIZE;
-    if (j->state == kQueued || j->state == kRunning) return RQA_EAGAIN;
-    return collect(srv, j, out, diag, vert, white);
+    hipEvent_t ev = nullptr;
+    int rc;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->jobs.find(ticket);
+        if (it == srv->jobs.end()) return RQA_ENOTFOUND;
+        ServedJob *j = it->second;
+        if ((diag || vert || white) && hist_len < j->n_vec + 1) return RQA_ESIZE;
+        if (j->state == kQueued || j->state == kRunning) return RQA_EAGAIN;
+        rc = collect(srv, j, out, diag, vert, white, &ev);
+    }
+    if (ev) hipEventDestroy(ev);
+    return rc;
 }
 
 int rqa_wait(rqa_server *srv, uint64_t ticket, rqa_measures *out, uint64_t *diag, uint64_t *vert,
              uint64_t *white, int64_t hist_len) {
     if (!srv) return RQA_EINVAL;
-    std::unique_lock<std::mutex> lk(srv->mu);
-    auto it = srv->jobs.find(ticket);
-    if (it == srv->jobs.end()) return RQA_ENOTFOUND;
-    ServedJob *j = it->second;
-    if ((diag || vert || white) && hist_len < j->n_vec + 1) return RQA_ESIZE;
-    srv->done_cv.wait(lk, [j] { return j->state == kDone || j->state == kFailed; });
-    return collect(srv, j, out, diag, vert, white);
+    hipEvent_t ev = nullptr;
+    int rc;
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        auto it = srv->jobs.find(ticket);
+        if (it == srv->jobs.end()) return RQA_ENOTFOUND;
+        ServedJob *j = it->second;
+        if ((diag || vert || white) && hist_len < j->n_vec + 1) return RQA_ESIZE;
+        srv->done_cv.wait(lk, [j] { return j->state == kDone || j->state == kFailed; });
+        rc = collect(srv, j, out, diag, vert, white, &ev);
+    }
+    if (ev) hipEventDestroy(ev);
+    return rc;
 }
 
 void rqa_server_destroy(rqa_server *srv) {
@@ -401,6 +450,7 @@ void rqa_server_destroy(rqa_server *srv) {
         hipEventDestroy(kv.second->ready);
         delete kv.second;
     }
+    for (auto &kv : srv->pinned_free) hipHostFree(kv.second);
     hipFree(srv->pool_base);
     delete srv;
 }

@@ -111,40 +111,41 @@ __device__ __forceinline__ uint64_t range_mask(uint32_t lo, uint32_t hi) {
     return a & b;
 }
 
-__device__ __forceinline__ uint32_t shfl_xor32(uint32_t v, int d) {
-    return (uint32_t)__shfl_xor((int)v, d, 64);
+// Lane exchange within 32-lane halves: lane l reads lane l^D (ds_swizzle in
+// xor mode; no VALU work).
+template <int D>
+__device__ __forceinline__ uint32_t swizzle_xor(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (D << 10));
 }
 
-// One butterfly stage of the bit-matrix transpose within 32-bit halves: lanes l
-// and l^D exchange the bit blocks selected by M (positions whose D-bit is 0) and
-// ~M.
+// One butterfly stage of the 64x64 bit transpose, D in {16,8,4,2,1}: lanes l and
+// l^D exchange bit blocks.  M marks the bit positions whose D-bit is 0.  The
+// lower lane keeps its M positions and takes the partner's M positions moved up
+// by D; the upper lane keeps its ~M positions and takes the partner's ~M
+// positions moved down by D.  The move is a rotation (v_alignbit); the bits it
+// wraps around fall outside the selected positions, so one v_bfi finishes the
+// stage.
 template <int D, uint32_t M>
 __device__ __forceinline__ void transpose_stage(uint32_t &lo, uint32_t &hi, int lane) {
-    const bool up = lane & D;
-    const uint32_t sl = up ? (lo & M) : (lo & ~M);
-    const uint32_t sh = up ? (hi & M) : (hi & ~M);
-    const uint32_t rl = shfl_xor32(sl, D);
-    const uint32_t rh = shfl_xor32(sh, D);
-    if (up) {
-        lo = (lo & ~M) | (rl >> D);
-        hi = (hi & ~M) | (rh >> D);
-    } else {
-        lo = (lo & M) | (rl << D);
-        hi = (hi & M) | (rh << D);
-    }
+    const bool up = (lane & D) != 0;
+    const uint32_t keep = up ? ~M : M;
+    const uint32_t amt = up ? (uint32_t)D : (uint32_t)(32 - D);
+    const uint32_t rl = swizzle_xor<D>(lo);
+    const uint32_t rh = swizzle_xor<D>(hi);
+    const uint32_t sl = __builtin_amdgcn_alignbit(rl, rl, amt);
+    const uint32_t sh = __builtin_amdgcn_alignbit(rh, rh, amt);
+    lo = (keep & lo) | (~keep & sl);
+    hi = (keep & hi) | (~keep & sh);
 }
 
 // In-register transpose of a 64x64 bit matrix held one row per lane: on return
-// lane l holds column l (bit r = old lane r's bit l).  Six butterfly stages; at
-// stage d the d-bit of the lane index is exchanged with the d-bit of the bit
-// position.
+// lane l holds column l (bit r = old lane r's bit l).  The 32-lane stage is one
+// v_permlane32_swap (upper lanes of `lo` <-> lower lanes of `hi`); the other five
+// stages are butterflies within 32-lane halves.
 __device__ __forceinline__ void transpose64(uint32_t &lo, uint32_t &hi, int lane) {
-    {   // d = 32: swap the 32-bit halves across lanes l and l^32
-        const bool up = lane & 32;
-        const uint32_t send = up ? lo : hi;
-        const uint32_t recv = shfl_xor32(send, 32);
-        if (up) lo = recv; else hi = recv;
-    }
+    const auto sw = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+    lo = sw[0];
+    hi = sw[1];
     transpose_stage<16, 0x0000FFFFu>(lo, hi, lane);
     transpose_stage<8, 0x00FF00FFu>(lo, hi, lane);
     transpose_stage<4, 0x0F0F0F0Fu>(lo, hi, lane);
@@ -152,16 +153,14 @@ __device__ __forceinline__ void transpose64(uint32_t &lo, uint32_t &hi, int lane
     transpose_stage<1, 0x55555555u>(lo, hi, lane);
 }
 
-// 64-bit rotate right by r (0..63).
+// 64-bit rotate right by r (0..63), branch-free.
 __device__ __forceinline__ void rotr64(uint32_t &lo, uint32_t &hi, uint32_t r) {
-    if (r & 32) { const uint32_t t = lo; lo = hi; hi = t; }
+    const bool sw = (r & 32) != 0;
+    const uint32_t a = sw ? hi : lo;
+    const uint32_t b = sw ? lo : hi;
     const uint32_t s = r & 31;
-    if (s) {
-        const uint32_t nl = __builtin_amdgcn_alignbit(hi, lo, s);
-        const uint32_t nh = __builtin_amdgcn_alignbit(lo, hi, s);
-        lo = nl;
-        hi = nh;
-    }
+    lo = __builtin_amdgcn_alignbit(b, a, s);
+    hi = __builtin_amdgcn_alignbit(a, b, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -236,25 +235,30 @@ __device__ __forceinline__ void finish_run(const LineCtx &lc, uint32_t c, uint32
     }
 }
 
-// Advance `st` over bits [lo, hi) of x, finishing every run that ends there.
+// Advance `st` over the bits [lo, hi) of x (win = mask of those bits),
+// finishing every run that ends there.  The common case -- no colour change in
+// the window -- costs a few VALU operations.
 template <int KIND>
-__device__ __forceinline__ void run_segment(uint64_t x, uint32_t lo, uint32_t hi, Run &st,
-                                            const LineCtx &lc) {
-    if (lo >= hi) return;
-    const uint64_t win = range_mask(lo, hi);
+__device__ __forceinline__ void run_segment(uint64_t x, uint64_t win, uint32_t lo, uint32_t hi,
+                                            Run &st, const LineCtx &lc) {
+    uint64_t diff = (st.color ? ~x : x) & win;
+    if (diff == 0) {
+        st.len += hi - lo;
+        return;
+    }
     uint32_t pos = lo;
     while (true) {
-        const uint64_t diff = (st.color ? ~x : x) & win & (~0ull << pos);
-        if (diff == 0) {
-            st.len += hi - pos;
-            break;
-        }
         const uint32_t p = (uint32_t)__builtin_ctzll(diff);
         finish_run<KIND>(lc, st.color, st.len + (p - pos), st.first);
         st.first = 0;
         st.color ^= 1u;
         st.len = 0;
         pos = p;
+        diff = (st.color ? ~x : x) & win & (~0ull << pos);
+        if (diff == 0) {
+            st.len = hi - pos;
+            return;
+        }
     }
 }
 
@@ -443,16 +447,24 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
             uint32_t xlo, xhi;
             tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, xlo, xhi);
 
-            // Valid cells of this row: columns [i + wp, n-1], rows < n.
-            int lo_v = i + wp - jbase;
-            lo_v = lo_v < 0 ? 0 : lo_v;
-            if (i >= n || lo_v > 64) lo_v = 64;
-            int hi_v = n - jbase;
-            hi_v = hi_v > 64 ? 64 : hi_v;
-            const uint64_t vmask = lo_v < hi_v ? range_mask(lo_v, hi_v) : 0ull;
-            uint64_t X = mk64(xlo, xhi) & vmask;
-            xlo = (uint32_t)X;
-            xhi = (uint32_t)(X >> 32);
+            // Interior tile: every row has started before this tile and every
+            // column continues below this wave, so no cell needs masking.
+            const bool interior = jbase >= R + 64 + wp && jbase + 63 <= n - 1;
+            int lo_v = 0, hi_v = 64;
+            uint64_t vmask = ~0ull;
+            uint64_t X = mk64(xlo, xhi);
+            if (!interior) {
+                // Valid cells of this row: columns [i + wp, n-1], rows < n.
+                lo_v = i + wp - jbase;
+                lo_v = lo_v < 0 ? 0 : lo_v;
+                if (i >= n || lo_v > 64) lo_v = 64;
+                hi_v = n - jbase;
+                hi_v = hi_v > 64 ? 64 : hi_v;
+                vmask = lo_v < hi_v ? range_mask(lo_v, hi_v) : 0ull;
+                X &= vmask;
+                xlo = (uint32_t)X;
+                xhi = (uint32_t)(X >> 32);
+            }
 
             // ---- horizontal runs (row i of U) ----
             if (lo_v < hi_v) {
@@ -461,7 +473,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                     hs = Run{(uint32_t)((X >> lo_v) & 1ull), 0u, 1u};
                 }
                 LineCtx lc{&j, bins, 0, false, (uint32_t)i};
-                run_segment<kHoriz>(X, (uint32_t)lo_v, (uint32_t)hi_v, hs, lc);
+                run_segment<kHoriz>(X, vmask, (uint32_t)lo_v, (uint32_t)hi_v, hs, lc);
             }
 
             const bool any = __ballot(X != 0ull) != 0ull;
@@ -473,15 +485,16 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                 else { ylo = 0; yhi = 0; }
                 const uint64_t Y = mk64(ylo, yhi);
                 const int jc = jbase + lane;
-                const int e = jc - wp - R;            // last valid local row of column jc
-                if (jc <= n - 1 && e >= 0) {
+                const int e = interior ? 64 : jc - wp - R;   // last valid local row of column jc
+                if (interior || (jc <= n - 1 && e >= 0)) {
                     const uint32_t vhi = e >= 63 ? 64u : (uint32_t)(e + 1);
                     Run st;
                     if (wave == 0) st = Run{(uint32_t)(Y & 1ull), 0u, 1u};
                     else st = unpack_run(L.vslot[(step - 1) & 1][wave - 1][lane]);
                     const int64_t sidx = soff + (jc - R0 - wp);
                     LineCtx lc{&j, bins, sidx, true, 0u};
-                    run_segment<kVert>(Y, 0u, vhi, st, lc);
+                    const uint64_t vwin = vhi >= 64 ? ~0ull : ((1ull << vhi) - 1ull);
+                    run_segment<kVert>(Y, vwin, 0u, vhi, st, lc);
                     if (e <= 63 || wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
                         j.vlast[sidx] = pk;
@@ -506,20 +519,33 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                 const int q = lane;
                 const int kup = jbase + q - R;          // diagonal of the upper part
                 const int klo = kup - 64;               // diagonal of the lower part
+                const uint64_t upwin = q == 0 ? ~0ull : ((1ull << (64 - q)) - 1ull);
                 Run up;
-                if (wave == 0) up = Run{(uint32_t)(D & 1ull), 0u, 1u};
-                else if (jbase + q > n - 1) up = Run{0u, 0u, 0u};   // starts past the border
-                else up = unpack_run(L.dslot[(step - 1) & 1][wave - 1][lane]);
+                if (wave == 0) {
+                    // Segment start on the strip's top row.  A white first cell
+                    // means "no black run at the top edge": record it at once
+                    // (white diagonal runs are never counted, so their length
+                    // does not matter).
+                    up = Run{(uint32_t)(D & 1ull), 0u, 1u};
+                    if (!up.color) {
+                        if (kup >= wp && kup <= n - 1 - R0) j.dfirst[soff + (kup - wp)] = 0;
+                        up.first = 0;
+                    }
+                } else if (jbase + q > n - 1) {
+                    up = Run{0u, 0u, 0u};   // starts past the border
+                } else {
+                    up = unpack_run(L.dslot[(step - 1) & 1][wave - 1][lane]);
+                }
                 {
                     const bool ok = kup >= wp && kup <= n - 1 - R0;
                     LineCtx lc{&j, bins, soff + (kup - wp), ok, 0u};
-                    run_segment<kDiag>(D, 0u, (uint32_t)(64 - q), up, lc);
+                    run_segment<kDiag>(D, upwin, 0u, (uint32_t)(64 - q), up, lc);
                 }
                 Run lw = left;
                 {
                     const bool ok = klo >= wp && klo <= n - 1 - R0;
                     LineCtx lc{&j, bins, soff + (klo - wp), ok, 0u};
-                    run_segment<kDiag>(D, (uint32_t)(64 - q), 64u, lw, lc);
+                    run_segment<kDiag>(D, ~upwin, (uint32_t)(64 - q), 64u, lw, lc);
                     // The lower part ends on row R+63.  Diagonals with no cell on
                     // the next row end here at the right border; the others go to
                     // the wave below or, from the last wave, into the summary.

@@ -1,0 +1,46 @@
+"""Write oracle histograms for full-size workloads that are too slow to
+recompute in every test run.  Calls only the CPU oracle (oracle/) and the
+seeded generators (workloads/); nothing here touches the HIP path.
+
+    python tests/golden/make_golden.py lorenz 0        # ~10-20 min on 8 cores
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+REPO = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, REPO)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from workloads import workload  # noqa: E402
+
+
+def sparse(h):
+    nz = np.nonzero(h)[0]
+    return {int(k): int(h[k]) for k in nz}
+
+
+def main(name, seed):
+    s, p = workload(name, seed=seed)
+    t0 = time.time()
+    (d, v, w), meas = oracle.rqa(s, p)
+    dt = time.time() - t0
+    out = {
+        "workload": name, "seed": seed, "n_points": len(s), "n_vec": len(d) - 1,
+        "params": p.asdict(), "oracle_seconds": round(dt, 1),
+        "series_sha_prefix": __import__("hashlib").sha256(s.tobytes()).hexdigest()[:16],
+        "diag": sparse(d), "vert": sparse(v), "white": sparse(w),
+        "measures": {k: (None if not np.isfinite(x) else x) for k, x in meas.items()},
+    }
+    path = os.path.join(HERE, f"{name}_seed{seed}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(path, f"{dt:.1f}s")
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 0)

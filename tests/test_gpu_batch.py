@@ -1,0 +1,96 @@
+"""Batched windowed RQA (GPU): every window of one batched launch equals the
+oracle on that window and the same window run alone; windows of uneven length,
+tiny windows and ragged tails are mixed in one launch."""
+import numpy as np
+import pytest
+
+from workloads import Params, windows_plan, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(tag, **kw):
+    print(f"[case] {tag} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def same_hist(res, ref, tag):
+    for name, a, b in (("diag", res.diag, ref[0]), ("vert", res.vert, ref[1]),
+                       ("white", res.white, ref[2])):
+        assert np.array_equal(a, b), f"{tag}: {name} differs at {np.nonzero(a != b)[0][:6]}"
+
+
+def test_batch_matches_oracle_and_single(cuda, oracle_lib):
+    import torch
+    from paper_2402_16853_amd import RQA
+    rng = np.random.default_rng(11)
+    s = rng.random(40_000).astype(np.float32)
+    p = Params(m=5, tau=2, eps=0.3, norm=1, theiler=1)
+    lengths = np.array([9, 10, 11, 64 + 8, 65 + 8, 700, 1000, 1500, 2047, 2500, 3100, 64 * 20 + 8]
+                       + list(rng.integers(1000, 3000, size=12)), dtype=np.int64)
+    offsets = np.array([rng.integers(0, len(s) - L + 1) for L in lengths], dtype=np.int64)
+    ds = torch.from_numpy(s).to(cuda)
+    comp = RQA.from_params(p)
+    _announce("batch", windows=len(lengths))
+    comp.run_batch(ds, offsets, lengths)
+    batch = [comp.result_batch(w) for w in range(len(lengths))]
+    single = RQA.from_params(p)
+    for w, (o, L) in enumerate(zip(offsets, lengths)):
+        win = s[o:o + L]
+        ref = oracle_lib.histograms(win, p.m, p.tau, p.eps, p.norm, p.theiler)
+        same_hist(batch[w], ref, f"window {w} len {L} vs oracle")
+        _announce("single", window=w, length=int(L))
+        alone = single(ds[int(o):int(o) + int(L)])
+        same_hist(batch[w], (alone.diag, alone.vert, alone.white), f"window {w} batch vs alone")
+        for k, v in alone.measures.items():
+            b = batch[w].measures[k]
+            assert (np.isnan(v) and np.isnan(b)) or v == b, (w, k)
+    comp.close()
+    single.close()
+
+
+def test_windowed_config_full(cuda, oracle_lib):
+    """Uniform noise N=500,000, 400 windows of 1,000..20,000 points, m=5, tau=2, L1,
+    eps=0.3: all 400 windows in one launch.  A sample of windows is checked
+    against the oracle; every window satisfies the histogram identities."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    s, p = workload("uniform", seed=0)
+    off, ln = windows_plan(len(s), 400, 1000, 20000, seed=0)
+    ds = torch.from_numpy(s).to(cuda)
+    comp = RQA.from_params(p)
+    _announce("windows400")
+    comp.run_batch(ds, off, ln)
+    res = [comp.result_batch(w) for w in range(len(off))]
+    for w, r in enumerate(res):
+        n = len(r.diag) - 1
+        L = np.arange(n + 1, dtype=np.float64)
+        assert (L * r.diag).sum() == (L * r.vert).sum(), w
+        assert (L * r.vert).sum() + (L * r.white).sum() == float(n) * n, w
+        assert np.all(r.diag % 2 == 0), w
+    order = np.argsort(ln)
+    sample = [int(order[0]), int(order[1]), int(order[len(order) // 2]), 7, 123]
+    for w in sample:
+        win = s[off[w]:off[w] + ln[w]]
+        ref = oracle_lib.histograms(win, p.m, p.tau, p.eps, p.norm, p.theiler)
+        same_hist(res[w], ref, f"window {w} len {ln[w]}")
+    comp.close()
+
+
+def test_repeat_and_shape_independence(cuda):
+    """Two launches with different workgroup shapes give identical results."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    s, p = workload("uniform", seed=1, n=60_000)
+    off, ln = windows_plan(len(s), 30, 500, 6000, seed=1)
+    ds = torch.from_numpy(s).to(cuda)
+    comp = RQA.from_params(p)
+    outs = []
+    for waves, groups in ((0, 0), (2, 5), (16, 1), (0, 0)):
+        _announce("repeat", waves=waves, groups=groups)
+        comp.set_tiling(waves, groups)
+        comp.run_batch(ds, off, ln)
+        outs.append([comp.result_batch(w) for w in range(len(off))])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            same_hist(a, (b.diag, b.vert, b.white), "shape/repeat")
+    comp.close()
