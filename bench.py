@@ -65,6 +65,19 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def settle(comp, run, fetch, limit=8):
+    """Setup before the warm-up: let the built-in autotuner time its candidate
+    workgroup shapes (each candidate is one complete run) until its choice is
+    stable, so that no tuning trial falls into the timed steps."""
+    seen = []
+    for _ in range(limit):
+        run()
+        fetch()
+        seen.append(comp.last_launch()["waves"])
+        if len(seen) >= 2 and seen[-1] == seen[-2]:
+            break
+
+
 def bench_headline(args, torch, RQA, workload):
     s, p = workload("lorenz", seed=args.seed)
     n = len(s) - (p.m - 1) * p.tau
@@ -85,7 +98,9 @@ def bench_headline(args, torch, RQA, workload):
             log(f"[sweep] waves={w} tiles {np.mean([x['tiles_ms'] for x in t]):.2f} ms "
                 f"stitch {np.mean([x['stitch_ms'] for x in t]):.2f} ms")
     comp.set_tiling(args.waves, 0)
-    log(f"[bench] lorenz N={len(s)} n_vec={n} eps={p.eps:.6g}; warmup {args.warmup}")
+    settle(comp, lambda: comp.run(ds), lambda: comp.result(histograms=False))
+    log(f"[bench] lorenz N={len(s)} n_vec={n} eps={p.eps:.6g} waves={comp.last_launch()['waves']}; "
+        f"warmup {args.warmup}")
     for _ in range(args.warmup):
         comp.run(ds)
         comp.result(histograms=True)
@@ -147,6 +162,12 @@ def bench_batched(args, torch, RQA, workload, windows_plan):
     nv = ln - (p.m - 1) * p.tau
     cells = float(np.sum(nv.astype(np.float64) ** 2))
     log(f"[bench] batched: {len(off)} windows, {cells:.3e} cells")
+
+    def fetch_all():
+        for w in range(len(off)):
+            comp.result_batch(w, histograms=False)
+
+    settle(comp, lambda: comp.run_batch(ds, off, ln), fetch_all)
     for _ in range(2):
         comp.run_batch(ds, off, ln)
         for w in range(len(off)):
@@ -239,14 +260,19 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-points", type=int, default=120_000)
+    ap.add_argument("--cpu-points", type=int, default=300_000)
     ap.add_argument("--requests", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
+    ap.add_argument("--only", default="", help="comma list of extra phases to run after the "
+                    "headline: batched, served, cpu (default: all)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = default)")
     ap.add_argument("--sweep", action="store_true", help="time the tile kernel per waves setting")
+    ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the RQA engine here is single-GPU); "
@@ -257,17 +283,31 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.probe_copy:
+        n = args.probe_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[probe] copied {args.probe_copy} MiB three times")
+        return
     from paper_2402_16853_amd import RQA, Server
     from workloads import workload, windows_plan, served_requests
 
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(phase, flag):
+        return not args.quick and not flag and (not only or phase in only)
+
     hl = bench_headline(args, torch, RQA, workload)
     extra = {}
-    if not args.quick and not args.no_batched:
+    if want("batched", args.no_batched):
         extra["batched"] = bench_batched(args, torch, RQA, workload, windows_plan)
-    if not args.quick and not args.no_served:
+    if want("served", args.no_served):
         extra["served"] = bench_served(args, torch, RQA, Server, served_requests)
     cpu = None
-    if not args.quick and not args.no_cpu:
+    if want("cpu", args.no_cpu):
         cpu = bench_cpu_baseline(args, hl)
 
     p = hl["p"]

@@ -135,9 +135,11 @@ int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert,
                            const uint64_t *white, int64_t n, const rqa_params *p,
                            rqa_measures *out);
 
-/* Tile-shape override used by the autotuner and by shape-independence tests:
- * waves per workgroup (1..16, rows per strip = 64*waves) and workgroups per
- * launch (0 = one per compute unit).  Results never depend on these. */
+/* Tile-shape override: waves per workgroup (1..16, rows per strip = 64*waves;
+ * 0 = chosen by the built-in autotuner, which times the candidate shapes on the
+ * first runs of each launch signature; RQA_AUTOTUNE_CACHE=<file> persists its
+ * choices) and workgroups per launch (0 = fill the device).  Results never
+ * depend on these. */
 int rqa_set_tiling(rqa_handle *h, int32_t waves_per_group, int32_t groups);
 
 /* Phase timing (hipEvents recorded on the run's stream).  With profiling on,
@@ -148,6 +150,12 @@ int rqa_set_tiling(rqa_handle *h, int32_t waves_per_group, int32_t groups);
  * output pointer may be NULL.  RQA_ESTATE if the last run was not profiled. */
 int rqa_set_profiling(rqa_handle *h, int32_t enable);
 int rqa_get_timings(rqa_handle *h, double *prepare_ms, double *tiles_ms, double *stitch_ms);
+
+/* How the last run was launched: waves per workgroup (chosen by the autotuner
+ * unless fixed with rqa_set_tiling) and whether it was replayed from a captured
+ * hipGraph (identical repeated launches are captured once and replayed).
+ * RQA_ESTATE before the first run. */
+int rqa_last_launch(const rqa_handle *h, int32_t *waves, int32_t *graph_replay);
 
 /* Release the handle and its device workspace (waits for outstanding work). */
 void rqa_destroy(rqa_handle *h);

@@ -52,6 +52,7 @@ SIGNATURES = {
     "rqa_get_timings": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),
+    "rqa_last_launch": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "rqa_destroy": (None, [_P]),
     "rqa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "rqa_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_size_t, _I32]),

@@ -4,9 +4,16 @@
 // are reported as errors, never aborts).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "rqa_internal.h"
@@ -66,6 +73,74 @@ int Workspace::reserve(size_t need) {
 
 using namespace rqa;
 
+// ---------------------------------------------------------------------------
+// Workgroup-shape autotuner.  For a launch signature (norm, m, size class,
+// number of jobs) it times each candidate shape on real runs (the tile phase,
+// measured with hipEvents when the run's result is fetched) and then keeps the
+// fastest.  Results never depend on the shape, so trial runs are ordinary runs.
+// The table is process-wide; with RQA_AUTOTUNE_CACHE=<file> decisions persist
+// across processes as "key waves" lines.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kCandidates[] = {2, 4, 8, 16};
+constexpr int kNumCandidates = 4;
+
+struct TuneEntry {
+    int next = 0;          // next candidate to try
+    int best = 0;          // best waves so far
+    double best_ms = 1e300;
+    bool done = false;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("RQA_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    std::string key;
+    int waves;
+    while (f >> key >> waves) {
+        if (waves < 1 || waves > 16) continue;
+        TuneEntry &e = g_tune[key];
+        e.best = waves;
+        e.done = true;
+    }
+}
+
+void tune_store_locked(const std::string &key, int waves) {
+    const char *path = std::getenv("RQA_AUTOTUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    f << key << " " << waves << "\n";
+}
+
+int ilog2(int64_t v) {
+    int l = 0;
+    while (v > 1) { v >>= 1; ++l; }
+    return l;
+}
+
+std::string tune_key(const rqa_params &p, int64_t nmax, int32_t count) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "norm%d_m%d_n2^%d_jobs2^%d_w%d", p.norm, p.m <= 6 ? p.m : 0,
+                  ilog2(nmax), ilog2(count), p.theiler > 64 ? 65 : p.theiler);
+    return buf;
+}
+
+uint64_t fnv(uint64_t h, const void *data, size_t bytes) {
+    const unsigned char *c = static_cast<const unsigned char *>(data);
+    for (size_t k = 0; k < bytes; ++k) h = (h ^ c[k]) * 1099511628211ull;
+    return h;
+}
+
+}  // namespace
+
 struct rqa_handle {
     rqa_params p{};
     Workspace ws;
@@ -75,20 +150,91 @@ struct rqa_handle {
     bool profiling = false;
     bool prof_valid = false;
     PhaseEvents prof{};
-    int waves = 0;                  // 0 = default tiling
-    int groups = 0;                 // 0 = one workgroup per compute unit
+    int waves = 0;                  // 0 = autotuned
+    int groups = 0;                 // 0 = fill the device
     bool has_run = false;
     bool batched = false;
     hipStream_t stream = nullptr;
     std::vector<int64_t> nvec;      // per job
-    std::vector<size_t> job_off;    // per job: byte offset of its region in ws.base
+    std::vector<size_t> job_off;    // per job: byte offset of its histograms in ws.base
+    size_t info_block_off = 0;      // info records (flag + statistics) of all jobs
+    size_t hist_block_off = 0;      // histograms of all jobs, contiguous
+    size_t hist_block_bytes = 0;
+    char *info_cache = nullptr;     // pinned host copies
+    size_t info_cache_bytes = 0;
+    uint64_t *host_cache = nullptr;
+    size_t host_cache_bytes = 0;
+    bool info_valid = false;
+    bool cache_valid = false;
+    bool last_from_graph = false;   // the last run was a graph replay
+    // autotuning trial in flight
+    bool trial = false;
+    int trial_waves = 0;
+    std::string trial_key;
+    // graph replay of repeated identical launches
+    uint64_t last_sig = 0;
+    uint64_t graph_sig = 0;
+    hipGraphExec_t graph = nullptr;
+    void *graph_staging = nullptr;
+    hipStream_t capture_stream = nullptr;
 };
 
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr size_t kFlagBytes = 256;
+void drop_graph(rqa_handle *h) {
+    if (h->graph) hipGraphExecDestroy(h->graph);
+    if (h->graph_staging) hipHostFree(h->graph_staging);
+    h->graph = nullptr;
+    h->graph_staging = nullptr;
+    h->graph_sig = 0;
+}
+
+int ensure_events(rqa_handle *h) {
+    if (!h->prof.ev[0]) {
+        for (hipEvent_t &e : h->prof.ev)
+            if (hipEventCreate(&e) != hipSuccess) return RQA_EDEVICE;
+    }
+    return RQA_OK;
+}
+
+// Capture the launch of `jobs` into a graph (own staging buffer, own capture
+// stream) and instantiate it.
+int capture_graph(rqa_handle *h, const std::vector<Job> &jobs, char *base, uint64_t sig) {
+    drop_graph(h);
+    if (!h->capture_stream &&
+        hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        return RQA_EDEVICE;
+    if (hipHostMalloc(&h->graph_staging, align256(engine_launch_scratch_bytes(jobs.size())),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph_staging = nullptr;
+        return RQA_ENOMEM;
+    }
+    if (hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return RQA_EDEVICE;
+    int rc = engine_launch(jobs, base, h->graph_staging, nullptr, h->groups, h->capture_stream,
+                           nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->capture_stream, &g);
+    if (rc != RQA_OK || ec != hipSuccess || !g) {
+        if (g) hipGraphDestroy(g);
+        (void)hipGetLastError();
+        drop_graph(h);
+        return rc != RQA_OK ? rc : RQA_EDEVICE;
+    }
+    const hipError_t ei = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph = nullptr;
+        drop_graph(h);
+        return RQA_EDEVICE;
+    }
+    h->graph_sig = sig;
+    return RQA_OK;
+}
 
 int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_t *offsets,
             const int64_t *lengths, int32_t count, void *stream, bool batched) {
@@ -97,7 +243,7 @@ int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_
     const KParams kp = make_kparams(h->p);
     std::vector<int64_t> nvec(count);
     std::vector<size_t> off(count);
-    size_t total = align256(engine_launch_scratch_bytes(count));
+    int64_t nmax = 0;
     for (int32_t w = 0; w < count; ++w) {
         const int64_t o = offsets ? offsets[w] : 0;
         const int64_t len = lengths ? lengths[w] : n_points;
@@ -111,12 +257,47 @@ int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_
         jb.n_vec = nv;
         jb.kp = kp;
         nvec[w] = nv;
-        off[w] = total;
-        total += align256(sizeof(uint64_t) * 3 * static_cast<size_t>(nv + 1)) + kFlagBytes +
-                 align256(engine_job_scratch_bytes(jb, h->waves));
+        nmax = std::max(nmax, nv);
     }
+
+    // Workgroup shape: fixed by rqa_set_tiling, else tuned per signature.
+    bool trial = false;
+    int waves = h->waves;
+    std::string key;
+    if (waves == 0) {
+        key = tune_key(h->p, nmax, count);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        TuneEntry &e = g_tune[key];
+        if (e.done) {
+            waves = e.best;
+        } else {
+            waves = kCandidates[e.next];
+            trial = true;
+        }
+    }
+    // Workspace: [launch scratch][info records of every job][histograms of every
+    // job][job scratch], so that a fetch copies the small records in one go and
+    // the histograms, when asked for, in one more.
+    size_t total = align256(engine_launch_scratch_bytes(count));
+    const size_t info_block_off = total;
+    total += align256(kInfoBytes * static_cast<size_t>(count));
+    const size_t hist_block_off = total;
+    for (int32_t w = 0; w < count; ++w) {
+        jobs[w].waves = waves;
+        off[w] = total;
+        total += align256(sizeof(uint64_t) * 3 * static_cast<size_t>(jobs[w].n_vec + 1));
+    }
+    const size_t hist_block_bytes = total - hist_block_off;
+    std::vector<size_t> soff(count);
+    for (int32_t w = 0; w < count; ++w) {
+        soff[w] = total;
+        total += align256(engine_job_scratch_bytes(jobs[w]));
+    }
+    void *old_base = h->ws.base;
     int rc = h->ws.reserve(total);
     if (rc != RQA_OK) return rc;
+    if (h->ws.base != old_base) drop_graph(h);
     const size_t stage = align256(engine_launch_scratch_bytes(count));
     if (!h->staging_free &&
         hipEventCreateWithFlags(&h->staging_free, hipEventDisableTiming) != hipSuccess)
@@ -135,27 +316,79 @@ int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_
     char *base = static_cast<char *>(h->ws.base);
     for (int32_t w = 0; w < count; ++w) {
         Job &jb = jobs[w];
-        char *p = base + off[w];
-        const size_t hb = align256(sizeof(uint64_t) * 3 * static_cast<size_t>(jb.n_vec + 1));
-        jb.hist = reinterpret_cast<uint64_t *>(p);
-        jb.flag = reinterpret_cast<int *>(p + hb);
-        jb.scratch = p + hb + kFlagBytes;
+        jb.hist = reinterpret_cast<uint64_t *>(base + off[w]);
+        jb.flag = reinterpret_cast<int *>(base + info_block_off + kInfoBytes * w);
+        jb.scratch = base + soff[w];
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (h->profiling && !h->prof.ev[0]) {
-        for (hipEvent_t &e : h->prof.ev)
-            if (hipEventCreate(&e) != hipSuccess) return RQA_EDEVICE;
+
+    // Signature of this launch: identical repeats replay a captured graph.
+    uint64_t sig = 1469598103934665603ull;
+    sig = fnv(sig, &d_series, sizeof d_series);
+    sig = fnv(sig, &n_points, sizeof n_points);
+    sig = fnv(sig, &count, sizeof count);
+    if (offsets) sig = fnv(sig, offsets, sizeof(int64_t) * count);
+    if (lengths) sig = fnv(sig, lengths, sizeof(int64_t) * count);
+    sig = fnv(sig, &h->p, sizeof h->p);
+    sig = fnv(sig, &waves, sizeof waves);
+    sig = fnv(sig, &h->groups, sizeof h->groups);
+    sig = fnv(sig, &base, sizeof base);
+    const bool plain = !h->profiling && !trial;
+
+    h->last_from_graph = false;
+    if (plain && h->graph && h->graph_sig == sig) {
+        if (hipGraphLaunch(h->graph, st) != hipSuccess) return RQA_EDEVICE;
+        h->prof_valid = false;
+        h->last_from_graph = true;
+    } else if (plain && h->last_sig == sig && capture_graph(h, jobs, base, sig) == RQA_OK) {
+        if (hipGraphLaunch(h->graph, st) != hipSuccess) return RQA_EDEVICE;
+        h->prof_valid = false;
+        h->last_from_graph = true;
+    } else {
+        const bool timed = h->profiling || trial;
+        if (timed && (rc = ensure_events(h)) != RQA_OK) return rc;
+        rc = engine_launch(jobs, base, h->staging, h->staging_free, h->groups, st,
+                           timed ? &h->prof : nullptr);
+        h->prof_valid = timed && rc == RQA_OK;
+        if (rc != RQA_OK) return rc;
     }
-    rc = engine_launch(jobs, base, h->staging, h->staging_free, h->waves, h->groups, st,
-                       h->profiling ? &h->prof : nullptr);
-    h->prof_valid = h->profiling && rc == RQA_OK;
-    if (rc != RQA_OK) return rc;
+    h->last_sig = sig;
+    h->trial = trial;
+    h->trial_waves = waves;
+    h->trial_key = key;
     h->nvec = std::move(nvec);
     h->job_off = std::move(off);
+    h->info_block_off = info_block_off;
+    h->hist_block_off = hist_block_off;
+    h->hist_block_bytes = hist_block_bytes;
+    h->info_valid = false;
+    h->cache_valid = false;
     h->stream = st;
     h->has_run = true;
     h->batched = batched;
     return RQA_OK;
+}
+
+// Record the tile-phase time of a finished autotuning trial.
+void finish_trial(rqa_handle *h) {
+    if (!h->trial) return;
+    h->trial = false;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->prof.ev[1], h->prof.ev[2]) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    TuneEntry &e = g_tune[h->trial_key];
+    if (e.done || kCandidates[e.next] != h->trial_waves) return;
+    if (ms < e.best_ms) {
+        e.best_ms = ms;
+        e.best = h->trial_waves;
+    }
+    if (++e.next == kNumCandidates) {
+        e.done = true;
+        tune_store_locked(h->trial_key, e.best);
+    }
 }
 
 int fetch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag, uint64_t *vert,
@@ -165,23 +398,60 @@ int fetch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag, uint6
     if (index < 0 || index >= static_cast<int32_t>(h->nvec.size())) return RQA_EINVAL;
     const int64_t n = h->nvec[index];
     if ((diag || vert || white) && hist_len < n + 1) return RQA_ESIZE;
-    if (hipStreamSynchronize(h->stream) != hipSuccess) return RQA_EDEVICE;
-    const char *p = static_cast<const char *>(h->ws.base) + h->job_off[index];
-    const size_t hb = align256(sizeof(uint64_t) * 3 * static_cast<size_t>(n + 1));
+    // Grow a pinned host buffer.
+    auto grow = [](void **buf, size_t *have, size_t need) -> int {
+        if (*have >= need) return RQA_OK;
+        if (*buf) hipHostFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+        if (hipHostMalloc(buf, need, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return RQA_ENOMEM;
+        }
+        *have = need;
+        return RQA_OK;
+    };
+    const size_t info_bytes = kInfoBytes * h->nvec.size();
+    if (!h->info_valid) {
+        // One copy of every job's flag and statistics.
+        int rc = grow(reinterpret_cast<void **>(&h->info_cache), &h->info_cache_bytes, info_bytes);
+        if (rc != RQA_OK) return rc;
+        if (hipMemcpyAsync(h->info_cache, static_cast<const char *>(h->ws.base) + h->info_block_off,
+                           info_bytes, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+            hipStreamSynchronize(h->stream) != hipSuccess)
+            return RQA_EDEVICE;
+        finish_trial(h);
+        h->info_valid = true;
+    }
+    const char *info = h->info_cache + kInfoBytes * static_cast<size_t>(index);
     int flag = 0;
-    if (hipMemcpy(&flag, p + hb, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
-        return RQA_EDEVICE;
+    std::memcpy(&flag, info, sizeof(int));
     if (flag & 1) return RQA_ENONFINITE;
     if (flag) return RQA_EDEVICE;   // internal consistency check failed on the device
-    std::vector<uint64_t> host(static_cast<size_t>(3 * (n + 1)));
-    if (hipMemcpy(host.data(), p, host.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
-        hipSuccess)
-        return RQA_EDEVICE;
-    const uint64_t *hd = host.data(), *hv = hd + (n + 1), *hw = hv + (n + 1);
-    if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * (n + 1));
-    if (vert) std::memcpy(vert, hv, sizeof(uint64_t) * (n + 1));
-    if (white) std::memcpy(white, hw, sizeof(uint64_t) * (n + 1));
-    if (out) measures_from_hist(hd, hv, hw, n, h->p, out);
+    if (diag || vert || white) {
+        if (!h->cache_valid) {
+            int rc = grow(reinterpret_cast<void **>(&h->host_cache), &h->host_cache_bytes,
+                          h->hist_block_bytes);
+            if (rc != RQA_OK) return rc;
+            if (hipMemcpyAsync(h->host_cache,
+                               static_cast<const char *>(h->ws.base) + h->hist_block_off,
+                               h->hist_block_bytes, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+                hipStreamSynchronize(h->stream) != hipSuccess)
+                return RQA_EDEVICE;
+            h->cache_valid = true;
+        }
+        const uint64_t *hd = reinterpret_cast<const uint64_t *>(
+            reinterpret_cast<const char *>(h->host_cache) + (h->job_off[index] - h->hist_block_off));
+        const uint64_t *hv = hd + (n + 1), *hw = hv + (n + 1);
+        if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * (n + 1));
+        if (vert) std::memcpy(vert, hv, sizeof(uint64_t) * (n + 1));
+        if (white) std::memcpy(white, hw, sizeof(uint64_t) * (n + 1));
+    }
+    if (out) {
+        JobStats st;
+        std::memcpy(&st, info + 8, sizeof st);
+        measures_from_stats(st, n, h->p, out);
+    }
     return RQA_OK;
 }
 
@@ -271,6 +541,14 @@ int rqa_get_timings(rqa_handle *h, double *prepare_ms, double *tiles_ms, double 
     return RQA_OK;
 }
 
+int rqa_last_launch(const rqa_handle *h, int32_t *waves, int32_t *graph_replay) {
+    if (!h) return RQA_EINVAL;
+    if (!h->has_run) return RQA_ESTATE;
+    if (waves) *waves = h->trial_waves;
+    if (graph_replay) *graph_replay = h->last_from_graph ? 1 : 0;
+    return RQA_OK;
+}
+
 void rqa_destroy(rqa_handle *h) {
     if (!h) return;
     if (h->has_run) hipStreamSynchronize(h->stream);
@@ -278,6 +556,10 @@ void rqa_destroy(rqa_handle *h) {
     if (h->staging_free) hipEventDestroy(h->staging_free);
     for (hipEvent_t e : h->prof.ev)
         if (e) hipEventDestroy(e);
+    drop_graph(h);
+    if (h->capture_stream) hipStreamDestroy(h->capture_stream);
+    if (h->host_cache) hipHostFree(h->host_cache);
+    if (h->info_cache) hipHostFree(h->info_cache);
     delete h;
 }
 

@@ -19,7 +19,24 @@ struct KParams {
     float eps_sq;   // fl32(eps*eps), L2 threshold on the squared sum
     int32_t norm;
     int32_t theiler;
+    int32_t lmin, vmin, wmin;   // minimum diagonal / vertical / white line lengths
 };
+
+// Per-job summary of the three histograms, reduced on the device: exact integer
+// moments and longest lines, and the FP64 entropies of the lines at or above the
+// minimum lengths (index 0 diagonal, 1 vertical, 2 white vertical).
+struct JobStats {
+    uint64_t cnt_all[3];    // number of lines
+    uint64_t mass_all[3];   // sum of their lengths
+    uint64_t cnt_min[3];    // number of lines of length >= minimum
+    uint64_t mass_min[3];   // sum of their lengths
+    uint64_t longest[3];    // longest line (0 if none)
+    double ent[3];          // -sum p ln p over lengths >= minimum, p = count / cnt_min
+};
+
+// Bytes of the per-job info record: int flag at offset 0, JobStats at 8.
+constexpr size_t kInfoBytes = 256;
+static_assert(8 + sizeof(JobStats) <= kInfoBytes, "info record too small");
 
 KParams make_kparams(const rqa_params &p);
 
@@ -29,9 +46,10 @@ struct Job {
     int64_t n_points = 0;           // points in the window
     int64_t n_vec = 0;              // delay vectors
     uint64_t *hist = nullptr;       // device: 3*(n_vec+1) u64 -- diag | vert | white
-    int *flag = nullptr;            // device int: set to 1 if the window is not finite
+    int *flag = nullptr;            // device info record (kInfoBytes): flag at 0, JobStats at 8
     void *scratch = nullptr;        // device: engine_job_scratch_bytes(*this) bytes
     KParams kp{};                   // parameters of this job
+    int waves = 0;                  // waves per workgroup (strip height 64*waves), > 0
 };
 
 // Device workspace owned by a handle (or a served job); grown on demand.
@@ -46,28 +64,49 @@ struct Workspace {
 // Device scratch one job needs beyond its histograms and flag (segment
 // summaries and line-end records), and the per-launch scratch (work
 // descriptors and the work counter) of a launch over `njobs` jobs.
-size_t engine_job_scratch_bytes(const Job &job, int waves);
+size_t engine_job_scratch_bytes(const Job &job);
 size_t engine_launch_scratch_bytes(size_t njobs);
 
-// Enqueue the full hot path for all jobs on `stream` as one batched pass:
-// validation, zeroing, the fused tile kernel, the stitch/join kernel.
-// `launch_scratch` holds engine_launch_scratch_bytes(jobs.size()) device bytes;
-// `staging` is pinned host memory of the same size; `staging_free` (may be
-// null) is an event the engine waits on before rewriting `staging` and records
-// once the launch has consumed it.  waves = 0 / groups = 0 pick defaults.
+// Default waves per workgroup for a job of n delay vectors.
+int engine_default_waves(int64_t n);
+
 // Optional phase events recorded on the launch stream: [0] before preparation,
 // [1] before the tile kernel(s), [2] after them, [3] after the stitch kernel.
 struct PhaseEvents {
     hipEvent_t ev[4];
 };
 
+// Enqueue the full hot path for all jobs on `stream` as one batched pass:
+// validation, zeroing, the fused tile kernel, the stitch/join kernel.
+// `launch_scratch` holds engine_launch_scratch_bytes(jobs.size()) device bytes;
+// `staging` is pinned host memory of the same size; `staging_free` (may be
+// null) is an event the engine waits on before rewriting `staging` and records
+// once the launch has consumed it.  Each job's `waves` fixes its strip height;
+// jobs are grouped per (norm, m, waves) into one tile-kernel launch each.
+// groups = 0 sizes each tile launch to fill the device.
+// Optional auxiliary streams: when a launch holds jobs of several (norm, m,
+// waves) groups, their tile kernels fork onto these streams and join back, so
+// small groups share the device instead of running one after another.
+struct AuxStreams {
+    static constexpr int kMax = 4;
+    int count = 0;
+    hipStream_t s[kMax] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kMax] = {};
+    int create(int n);    // RQA_OK or RQA_EDEVICE
+    void destroy();
+};
+
 int engine_launch(const std::vector<Job> &jobs, void *launch_scratch, void *staging,
-                  hipEvent_t staging_free, int waves, int groups, hipStream_t stream,
-                  const PhaseEvents *phases = nullptr);
+                  hipEvent_t staging_free, int groups, hipStream_t stream,
+                  const PhaseEvents *phases = nullptr, AuxStreams *aux = nullptr);
 
 // Host FP64 measures from histograms of length n+1.
 void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
                         int64_t n, const rqa_params &p, rqa_measures *out);
+
+// Host FP64 measures from the device-reduced statistics.
+void measures_from_stats(const JobStats &st, int64_t n, const rqa_params &p, rqa_measures *out);
 
 int validate_params(const rqa_params &p);
 

@@ -18,23 +18,6 @@ struct Moments {
     double mass = 0.0;    // sum of their lengths
 };
 
-Moments moments(const uint64_t *h, int64_t n, int64_t floor_len) {
-    Moments mo;
-    for (int64_t l = floor_len < 1 ? 1 : floor_len; l <= n; ++l) {
-        if (h[l] == 0) continue;
-        const double c = static_cast<double>(h[l]);
-        mo.count += c;
-        mo.mass += c * static_cast<double>(l);
-    }
-    return mo;
-}
-
-double longest(const uint64_t *h, int64_t n) {
-    for (int64_t l = n; l >= 1; --l)
-        if (h[l] != 0) return static_cast<double>(l);
-    return 0.0;
-}
-
 // Shannon entropy (natural log) of the distribution of lines of length >= floor.
 double entropy(const uint64_t *h, int64_t n, int64_t floor_len, double count) {
     if (count == 0.0) return std::numeric_limits<double>::quiet_NaN();
@@ -63,33 +46,76 @@ double cells_outside_band(int64_t n, int64_t w) {
     return nn - band;
 }
 
+// Count, mass (sum of lengths), longest line and the count/mass over lengths
+// >= floor, in one ascending pass.
+struct Stats {
+    Moments all;
+    Moments min;
+    double longest = 0.0;
+};
+
+Stats scan(const uint64_t *h, int64_t n, int64_t floor_len) {
+    Stats st;
+    for (int64_t l = 1; l <= n; ++l) {
+        if (h[l] == 0) continue;
+        const double c = static_cast<double>(h[l]);
+        const double m = c * static_cast<double>(l);
+        st.all.count += c;
+        st.all.mass += m;
+        if (l >= floor_len) {
+            st.min.count += c;
+            st.min.mass += m;
+        }
+        st.longest = static_cast<double>(l);
+    }
+    return st;
+}
+
 }  // namespace
 
 void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
                         int64_t n, const rqa_params &p, rqa_measures *out) {
-    const Moments d_all = moments(diag, n, 1);
-    const Moments d_min = moments(diag, n, p.lmin);
-    const Moments v_all = moments(vert, n, 1);
-    const Moments v_min = moments(vert, n, p.vmin);
-    const Moments w_min = moments(white, n, p.wmin);
+    const Stats d = scan(diag, n, p.lmin);
+    const Stats v = scan(vert, n, p.vmin);
+    const Stats w = scan(white, n, p.wmin);
 
     out->n_vec = n;
     out->n_rec = 0;
     for (int64_t l = 1; l <= n; ++l) out->n_rec += diag[l] * static_cast<uint64_t>(l);
 
-    out->rr = ratio(d_all.mass, cells_outside_band(n, p.theiler));
-    out->det = ratio(d_min.mass, d_all.mass);
-    out->l = ratio(d_min.mass, d_min.count);
-    out->lmax = longest(diag, n);
+    out->rr = ratio(d.all.mass, cells_outside_band(n, p.theiler));
+    out->det = ratio(d.min.mass, d.all.mass);
+    out->l = ratio(d.min.mass, d.min.count);
+    out->lmax = d.longest;
     out->div = out->lmax == 0.0 ? std::numeric_limits<double>::quiet_NaN() : 1.0 / out->lmax;
-    out->l_entr = entropy(diag, n, p.lmin, d_min.count);
-    out->lam = ratio(v_min.mass, v_all.mass);
-    out->tt = ratio(v_min.mass, v_min.count);
-    out->vmax = longest(vert, n);
-    out->v_entr = entropy(vert, n, p.vmin, v_min.count);
-    out->w = ratio(w_min.mass, w_min.count);
-    out->wmax = longest(white, n);
-    out->w_entr = entropy(white, n, p.wmin, w_min.count);
+    out->l_entr = entropy(diag, n, p.lmin, d.min.count);
+    out->lam = ratio(v.min.mass, v.all.mass);
+    out->tt = ratio(v.min.mass, v.min.count);
+    out->vmax = v.longest;
+    out->v_entr = entropy(vert, n, p.vmin, v.min.count);
+    out->w = ratio(w.min.mass, w.min.count);
+    out->wmax = w.longest;
+    out->w_entr = entropy(white, n, p.wmin, w.min.count);
+}
+
+void measures_from_stats(const JobStats &st, int64_t n, const rqa_params &p, rqa_measures *out) {
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    auto dbl = [](uint64_t v) { return static_cast<double>(v); };
+    out->n_vec = n;
+    out->n_rec = st.mass_all[0];
+    out->rr = ratio(dbl(st.mass_all[0]), cells_outside_band(n, p.theiler));
+    out->det = ratio(dbl(st.mass_min[0]), dbl(st.mass_all[0]));
+    out->l = ratio(dbl(st.mass_min[0]), dbl(st.cnt_min[0]));
+    out->lmax = dbl(st.longest[0]);
+    out->div = st.longest[0] == 0 ? nan : 1.0 / out->lmax;
+    out->l_entr = st.cnt_min[0] ? st.ent[0] : nan;
+    out->lam = ratio(dbl(st.mass_min[1]), dbl(st.mass_all[1]));
+    out->tt = ratio(dbl(st.mass_min[1]), dbl(st.cnt_min[1]));
+    out->vmax = dbl(st.longest[1]);
+    out->v_entr = st.cnt_min[1] ? st.ent[1] : nan;
+    out->w = ratio(dbl(st.mass_min[2]), dbl(st.cnt_min[2]));
+    out->wmax = dbl(st.longest[2]);
+    out->w_entr = st.cnt_min[2] ? st.ent[2] : nan;
 }
 
 }  // namespace rqa

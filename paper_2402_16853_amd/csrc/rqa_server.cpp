@@ -89,14 +89,14 @@ struct ServedJob {
     size_t hist_bytes = 0;
     size_t off = 0;
     hipEvent_t ready = nullptr;    // recorded on the caller's stream at submit
-    uint64_t *host = nullptr;      // pinned: 3*(n+1) histograms + flag word
+    uint64_t *host = nullptr;      // pinned: 3*(n+1) histograms + info record
     size_t host_bytes = 0;
     int state = kQueued;
     int rc = RQA_OK;
 };
 
 constexpr size_t kMaxBatch = 256;
-constexpr size_t kFlagBytes = 256;
+constexpr size_t kInfoWords = kInfoBytes / sizeof(uint64_t);
 
 }  // namespace
 
@@ -112,6 +112,7 @@ struct rqa_server {
     std::vector<char *> launch_scratch;   // per stream, device
     std::vector<void *> staging;          // per stream, pinned host
     std::vector<hipEvent_t> staging_free; // per stream: staging consumed
+    std::vector<AuxStreams> aux;          // per stream: fork streams for mixed groups
     size_t next_stream = 0;
     std::deque<ServedJob *> pending;
     std::unordered_map<uint64_t, ServedJob *> jobs;
@@ -139,7 +140,8 @@ size_t job_scratch_bytes(const rqa_params &p, int64_t n_points, int64_t n_vec) {
     one.n_points = n_points;
     one.n_vec = n_vec;
     one.kp = make_kparams(p);
-    return align256(engine_job_scratch_bytes(one, 0));
+    one.waves = engine_default_waves(n_vec);
+    return align256(engine_job_scratch_bytes(one));
 }
 
 // Pinned buffer of at least `bytes` from the cache (lock held), or nullptr.
@@ -158,7 +160,8 @@ void on_launch_done(void *arg) {
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         for (ServedJob *j : ln->jobs) {
-            const int flag = static_cast<int>(j->host[3 * (j->n_vec + 1)]);
+            int flag = 0;
+            std::memcpy(&flag, j->host + 3 * (j->n_vec + 1), sizeof(int));
             j->rc = (flag & 1) ? RQA_ENONFINITE : flag ? RQA_EDEVICE : RQA_OK;
             j->state = flag ? kFailed : kDone;
             srv->pool.release(j->off, j->footprint);
@@ -204,18 +207,19 @@ size_t admit_and_launch(rqa_server *srv, std::unique_lock<std::mutex> &lk) {
         e.n_vec = j->n_vec;
         e.hist = reinterpret_cast<uint64_t *>(base);
         e.flag = reinterpret_cast<int *>(base + j->hist_bytes);
-        e.scratch = base + j->hist_bytes + kFlagBytes;
+        e.scratch = base + j->hist_bytes + kInfoBytes;
         e.kp = make_kparams(j->p);
+        e.waves = engine_default_waves(j->n_vec);
         ej.push_back(e);
     }
     if (rc == RQA_OK)
         rc = engine_launch(ej, srv->launch_scratch[slot], srv->staging[slot],
-                           srv->staging_free[slot], 0, 0, st);
+                           srv->staging_free[slot], 0, st, nullptr, &srv->aux[slot]);
     for (size_t k = 0; k < batch.size() && rc == RQA_OK; ++k) {
         ServedJob *j = batch[k];
         const size_t hb = sizeof(uint64_t) * 3 * static_cast<size_t>(j->n_vec + 1);
         if (hipMemcpyAsync(j->host, ej[k].hist, hb, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(j->host + 3 * (j->n_vec + 1), ej[k].flag, sizeof(int),
+            hipMemcpyAsync(j->host + 3 * (j->n_vec + 1), ej[k].flag, kInfoBytes,
                            hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = RQA_EDEVICE;
     }
@@ -277,7 +281,11 @@ int collect(rqa_server *srv, ServedJob *j, rqa_measures *out, uint64_t *diag, ui
         if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * (n + 1));
         if (vert) std::memcpy(vert, hv, sizeof(uint64_t) * (n + 1));
         if (white) std::memcpy(white, hw, sizeof(uint64_t) * (n + 1));
-        if (out) measures_from_hist(hd, hv, hw, n, j->p, out);
+        if (out) {
+            JobStats stats;
+            std::memcpy(&stats, reinterpret_cast<const char *>(hw + (n + 1)) + 8, sizeof stats);
+            measures_from_stats(stats, n, j->p, out);
+        }
     }
     srv->jobs.erase(j->ticket);
     srv->pinned_free.emplace(j->host_bytes, j->host);
@@ -296,7 +304,7 @@ int rqa_job_footprint(const rqa_params *p, int64_t n_points, size_t *bytes) {
     if (rc != RQA_OK) return rc;
     const int64_t nv = n_points - static_cast<int64_t>(p->m - 1) * p->tau;
     if (nv < 1) return RQA_ETOOSHORT;
-    *bytes = job_hist_bytes(nv) + kFlagBytes + job_scratch_bytes(*p, n_points, nv);
+    *bytes = job_hist_bytes(nv) + kInfoBytes + job_scratch_bytes(*p, n_points, nv);
     return RQA_OK;
 }
 
@@ -327,6 +335,8 @@ int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams) {
         hipEvent_t ev = nullptr;
         ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
         if (ok) srv->staging_free.push_back(ev);
+        srv->aux.emplace_back();
+        ok = ok && srv->aux.back().create(3) == RQA_OK;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -334,6 +344,7 @@ int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams) {
         for (char *d : srv->launch_scratch) hipFree(d);
         for (void *h : srv->staging) hipHostFree(h);
         for (hipEvent_t e : srv->staging_free) hipEventDestroy(e);
+        for (AuxStreams &a : srv->aux) a.destroy();
         hipFree(base);
         return RQA_ENOMEM;
     }
@@ -358,7 +369,7 @@ int rqa_submit(rqa_server *srv, const rqa_params *p, const float *d_series, int6
     j->n_vec = n_points - static_cast<int64_t>(p->m - 1) * p->tau;
     j->footprint = fp;
     j->hist_bytes = job_hist_bytes(j->n_vec);
-    const size_t need = sizeof(uint64_t) * (3 * static_cast<size_t>(j->n_vec + 1) + 1);
+    const size_t need = sizeof(uint64_t) * (3 * static_cast<size_t>(j->n_vec + 1) + kInfoWords);
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         j->host = static_cast<uint64_t *>(take_pinned(srv, need, &j->host_bytes));
@@ -374,7 +385,7 @@ int rqa_submit(rqa_server *srv, const rqa_params *p, const float *d_series, int6
         }
         j->host_bytes = cap;
     }
-    j->host[3 * (j->n_vec + 1)] = 0;
+    std::memset(j->host + 3 * (j->n_vec + 1), 0, kInfoBytes);
     if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(j->ready, static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
         std::lock_guard<std::mutex> lk(srv->mu);
@@ -445,6 +456,10 @@ void rqa_server_destroy(rqa_server *srv) {
     for (char *d : srv->launch_scratch) hipFree(d);
     for (void *h : srv->staging) hipHostFree(h);
     for (hipEvent_t e : srv->staging_free) hipEventDestroy(e);
+    for (AuxStreams &a : srv->aux) {
+        for (int k = 0; k < a.count; ++k) hipStreamSynchronize(a.s[k]);
+        a.destroy();
+    }
     for (auto &kv : srv->jobs) {
         hipHostFree(kv.second->host);
         hipEventDestroy(kv.second->ready);

@@ -48,6 +48,9 @@ KParams make_kparams(const rqa_params &p) {
     k.eps_sq = e * e;
     k.norm = p.norm;
     k.theiler = p.theiler;
+    k.lmin = p.lmin;
+    k.vmin = p.vmin;
+    k.wmin = p.wmin;
     return k;
 }
 
@@ -59,6 +62,8 @@ constexpr int kCapV = 1024;    // LDS bins for vertical lengths < kCapV
 constexpr int kCapW = 6144;    // LDS bins for white-vertical lengths < kCapW
 constexpr int kMaxM = 6;       // embedding dimensions held in registers
 constexpr int kStitchThreads = 256;
+constexpr int kStatThreads = 256;
+constexpr int kStatMaxBlocks = 64;
 
 // Device-side description of one job (one series or window).
 struct JobDesc {
@@ -83,6 +88,10 @@ struct JobDesc {
     int32_t tail_len;          // floats in tail
     int32_t strip_base;        // first work item of this job within its group
     int32_t stitch_block0;     // first stitch block of this job
+    int32_t mins[3];           // lmin, vmin, wmin
+    int32_t stat_blocks;       // blocks of the statistics kernels for this job
+    JobStats *stats;           // device statistics record
+    double *ent_part;          // [3][kStatMaxBlocks] entropy partial sums
 };
 
 struct GroupDesc {
@@ -365,6 +374,8 @@ __global__ void k_prepare(const JobDesc *__restrict__ jobs) {
         j.hv[t] = 0ull;
         j.hw[t] = 0ull;
     }
+    if (tid < (int64_t)(sizeof(JobStats) / 8))
+        reinterpret_cast<unsigned long long *>(j.stats)[tid] = 0ull;
     bool bad = false;
     for (int64_t t = tid; t < j.n_points; t += stride) bad |= !__builtin_isfinite(j.s[t]);
     if (bad) atomicOr(j.flag, 1);   // bit 0: non-finite input
@@ -717,6 +728,108 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Kernels 4-6: statistics of the finished histograms (the inputs of the RQA
+// measures), so that a result fetch needs only a few hundred bytes.  Integer
+// moments are exact (u64); the entropy partial sums use a fixed reduction
+// order, so a job's statistics depend only on its own histograms.
+// grid = (kStatMaxBlocks, jobs); block b of a job covers one contiguous chunk of
+// lengths.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void chunk_of(const JobDesc &j, int b, int64_t &lo, int64_t &hi) {
+    const int64_t len = (int64_t)j.n + 1;
+    const int64_t per = (len + j.stat_blocks - 1) / j.stat_blocks;
+    lo = (int64_t)b * per;
+    hi = lo + per < len ? lo + per : len;
+}
+
+__global__ void __launch_bounds__(kStatThreads) k_stats_moments(const JobDesc *__restrict__ jobs) {
+    const JobDesc &j = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= j.stat_blocks) return;
+    __shared__ unsigned long long red[5][kStatThreads];
+    int64_t lo, hi;
+    chunk_of(j, blockIdx.x, lo, hi);
+    const unsigned long long *hs[3] = {j.hd, j.hv, j.hw};
+    for (int h = 0; h < 3; ++h) {
+        unsigned long long ca = 0, ma = 0, cm = 0, mm = 0, lg = 0;
+        for (int64_t l = lo + threadIdx.x; l < hi; l += kStatThreads) {
+            const unsigned long long c = hs[h][l];
+            if (l == 0 || c == 0) continue;
+            ca += c;
+            ma += c * (unsigned long long)l;
+            if (l >= j.mins[h]) {
+                cm += c;
+                mm += c * (unsigned long long)l;
+            }
+            lg = (unsigned long long)l;
+        }
+        red[0][threadIdx.x] = ca;
+        red[1][threadIdx.x] = ma;
+        red[2][threadIdx.x] = cm;
+        red[3][threadIdx.x] = mm;
+        red[4][threadIdx.x] = lg;
+        __syncthreads();
+        for (int s = kStatThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) {
+                for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+                red[4][threadIdx.x] = red[4][threadIdx.x] > red[4][threadIdx.x + s]
+                                          ? red[4][threadIdx.x] : red[4][threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            JobStats *st = j.stats;
+            if (red[0][0]) atomicAdd(&st->cnt_all[h], red[0][0]);
+            if (red[1][0]) atomicAdd(&st->mass_all[h], red[1][0]);
+            if (red[2][0]) atomicAdd(&st->cnt_min[h], red[2][0]);
+            if (red[3][0]) atomicAdd(&st->mass_min[h], red[3][0]);
+            if (red[4][0]) atomicMax(&st->longest[h], red[4][0]);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kStatThreads) k_stats_entropy(const JobDesc *__restrict__ jobs) {
+    const JobDesc &j = jobs[blockIdx.y];
+    if ((int)blockIdx.x >= j.stat_blocks) return;
+    __shared__ double red[kStatThreads];
+    int64_t lo, hi;
+    chunk_of(j, blockIdx.x, lo, hi);
+    const unsigned long long *hs[3] = {j.hd, j.hv, j.hw};
+    for (int h = 0; h < 3; ++h) {
+        const unsigned long long total = j.stats->cnt_min[h];
+        double acc = 0.0;
+        if (total) {
+            const double C = (double)total;
+            const int64_t from = lo > j.mins[h] ? lo : (int64_t)j.mins[h];
+            for (int64_t l = from + threadIdx.x; l < hi; l += kStatThreads) {
+                const unsigned long long c = hs[h][l];
+                if (l == 0 || c == 0) continue;
+                const double p = (double)c / C;
+                acc -= p * log(p);
+            }
+        }
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int s = kStatThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) j.ent_part[h * kStatMaxBlocks + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_stats_final(const JobDesc *__restrict__ jobs, int njobs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * njobs) return;
+    const JobDesc &j = jobs[t / 3];
+    const int h = t % 3;
+    double e = 0.0;
+    for (int b = 0; b < j.stat_blocks; ++b) e = e + j.ent_part[h * kStatMaxBlocks + b];
+    j.stats->ent[h] = e;
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 using TileKernel = void (*)(const JobDesc *, const GroupDesc *, int, int *);
@@ -740,30 +853,31 @@ TileKernel tile_kernel(int norm, int m) {
     return pick_kernel<RQA_NORM_LINF>(m);
 }
 
-int group_key(const KParams &kp) { return kp.norm * 16 + (kp.m <= kMaxM ? kp.m : 0); }
+int group_key(const Job &jb) {
+    return (jb.kp.norm * 16 + (jb.kp.m <= kMaxM ? jb.kp.m : 0)) * 32 + jb.waves;
+}
 
 struct Layout {
     int H, nstrips;
     int64_t entries;       // summary entries per array
     int64_t tail_len;
-    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, bytes;
+    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, bytes;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int default_waves(int64_t n) {
-    // Tall strips amortise the strip-edge summaries; short series use fewer waves
-    // per strip so that more strips are available.
-    if (n >= 16 * 1024 * 64) return 16;
+int default_waves_impl(int64_t n) {
+    // Eight waves per workgroup (two workgroups per compute unit) measured
+    // fastest for long series; short series use four so that more strips exist.
     if (n >= 4096 * 8) return 8;
     return 4;
 }
 
-Layout layout_of(const Job &jb, int waves) {
+Layout layout_of(const Job &jb) {
     Layout L{};
     const int64_t n = jb.n_vec;
     const int wp = jb.kp.theiler > 1 ? jb.kp.theiler : 1;
-    L.H = 64 * (waves > 0 ? waves : default_waves(n));
+    L.H = 64 * (jb.waves > 0 ? jb.waves : default_waves_impl(n));
     L.nstrips = n - wp > 0 ? (int)((n - wp + L.H - 1) / L.H) : 0;
     // sum over strips of (n - wp - s H) entries
     L.entries = (int64_t)L.nstrips * (n - wp) - (int64_t)L.H * ((int64_t)L.nstrips * (L.nstrips - 1) / 2);
@@ -778,45 +892,72 @@ Layout layout_of(const Job &jb, int waves) {
     L.off_vl = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
     L.off_df = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
     L.off_dl = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
+    L.off_ent = off; off += a256(sizeof(double) * 3 * kStatMaxBlocks);
     L.bytes = off;
     return L;
 }
 
 }  // namespace
 
-size_t engine_job_scratch_bytes(const Job &job, int waves) { return layout_of(job, waves).bytes; }
+size_t engine_job_scratch_bytes(const Job &job) { return layout_of(job).bytes; }
+
+int engine_default_waves(int64_t n) { return default_waves_impl(n); }
 
 size_t engine_launch_scratch_bytes(size_t njobs) {
     return a256(sizeof(JobDesc) * njobs) + a256(sizeof(GroupDesc) * 64) + 256;
 }
 
+int AuxStreams::create(int n) {
+    n = n < kMax ? n : kMax;
+    for (int k = 0; k < n; ++k) {
+        if (hipStreamCreateWithFlags(&s[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&join[k], hipEventDisableTiming) != hipSuccess) {
+            count = k;
+            destroy();
+            return RQA_EDEVICE;
+        }
+        count = k + 1;
+    }
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+        destroy();
+        return RQA_EDEVICE;
+    }
+    return RQA_OK;
+}
+
+void AuxStreams::destroy() {
+    for (int k = 0; k < count; ++k) {
+        if (s[k]) hipStreamDestroy(s[k]);
+        if (join[k]) hipEventDestroy(join[k]);
+        s[k] = nullptr;
+        join[k] = nullptr;
+    }
+    if (fork) hipEventDestroy(fork);
+    fork = nullptr;
+    count = 0;
+}
+
 int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *staging,
-                  hipEvent_t staging_free, int waves, int groups_req, hipStream_t st,
-                  const PhaseEvents *phases) {
+                  hipEvent_t staging_free, int groups_req, hipStream_t st,
+                  const PhaseEvents *phases, AuxStreams *aux) {
     const int njobs = (int)jobs_in.size();
     if (njobs == 0) return RQA_OK;
+    for (const Job &jb : jobs_in)
+        if (jb.waves < 1 || jb.waves > kMaxWaves) return RQA_EINVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return RQA_EDEVICE;
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return RQA_EDEVICE;
 
-    // Order: by (norm, m) group, then by decreasing size (largest strips first).
+    // Order: by (norm, m, waves) group, then by decreasing size (largest strips first).
     std::vector<int> order(njobs);
     for (int k = 0; k < njobs; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const int ga = group_key(jobs_in[a].kp), gb = group_key(jobs_in[b].kp);
+        const int ga = group_key(jobs_in[a]), gb = group_key(jobs_in[b]);
         if (ga != gb) return ga < gb;
         return jobs_in[a].n_vec > jobs_in[b].n_vec;
     });
-
-    // Waves per workgroup: one value per launch (the workgroup size).
-    int w = waves;
-    if (w <= 0) {
-        int64_t nmax = 0;
-        for (const Job &jb : jobs_in) nmax = std::max<int64_t>(nmax, jb.n_vec);
-        w = default_waves(nmax);
-    }
 
     // The previous launch that used `staging` must have consumed it.
     if (staging_free && hipEventSynchronize(staging_free) != hipSuccess) return RQA_EDEVICE;
@@ -837,8 +978,8 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     for (int r = 0; r < njobs; ++r) {
         const Job &jb = jobs_in[order[r]];
         const KParams &kp = jb.kp;
-        const Layout lay = layout_of(jb, w);
-        const int key = group_key(kp);
+        const Layout lay = layout_of(jb);
+        const int key = group_key(jb);
         if (ngroups == 0 || gkeys.back() != key) {
             if (ngroups == 64) return RQA_EINVAL;
             if (ngroups > 0) hgroups[ngroups - 1].items = strip_acc;
@@ -875,6 +1016,12 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         d.tail_len = (int32_t)lay.tail_len;
         d.strip_base = strip_acc;
         d.stitch_block0 = stitch_blocks;
+        d.mins[0] = kp.lmin;
+        d.mins[1] = kp.vmin;
+        d.mins[2] = kp.wmin;
+        d.stat_blocks = (int32_t)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (jb.n_vec + 1 + 8191) / 8192));
+        d.stats = reinterpret_cast<JobStats *>(reinterpret_cast<char *>(jb.flag) + 8);
+        d.ent_part = reinterpret_cast<double *>(scr + lay.off_ent);
         strip_acc += lay.nstrips;
         stitch_blocks += (int)((2 * jb.n_vec + kStitchThreads - 1) / kStitchThreads);
         hdesc[r] = d;
@@ -892,10 +1039,17 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     hipLaunchKernelGGL(k_prepare, dim3(64, njobs), dim3(256), 0, st, ddesc);
 
     if (phases) hipEventRecord(phases->ev[1], st);
+    int active = 0;
+    for (int g = 0; g < ngroups; ++g) active += hgroups[g].items > 0;
+    const bool fork = aux && aux->count > 0 && active > 1;
+    if (fork) hipEventRecord(aux->fork, st);
+    bool used[AuxStreams::kMax] = {};
+    int launched = 0;
     for (int g = 0; g < ngroups; ++g) {
         const GroupDesc &gd = hgroups[g];
         if (gd.items == 0) continue;
         const KParams &kp = jobs_in[order[gd.job0]].kp;
+        const int w = jobs_in[order[gd.job0]].waves;
         TileKernel kern = tile_kernel(kp.norm, kp.m);
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, 0) != hipSuccess ||
@@ -903,11 +1057,30 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
             occ = 1;
         int grid = groups_req > 0 ? groups_req : ncu * occ;
         grid = std::min(grid, gd.items);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), 0, st, ddesc, dgroups, g, dcounters);
+        // The first group runs on the launch stream; further groups fork.
+        hipStream_t gs = st;
+        if (fork && launched > 0) {
+            const int k = (launched - 1) % aux->count;
+            gs = aux->s[k];
+            if (!used[k]) hipStreamWaitEvent(gs, aux->fork, 0);
+            used[k] = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), 0, gs, ddesc, dgroups, g, dcounters);
+        ++launched;
+    }
+    if (fork) {
+        for (int k = 0; k < aux->count; ++k) {
+            if (!used[k]) continue;
+            hipEventRecord(aux->join[k], aux->s[k]);
+            hipStreamWaitEvent(st, aux->join[k], 0);
+        }
     }
     if (phases) hipEventRecord(phases->ev[2], st);
     if (stitch_blocks > 0)
         hipLaunchKernelGGL(k_stitch, dim3(stitch_blocks), dim3(kStitchThreads), 0, st, ddesc, njobs);
+    hipLaunchKernelGGL(k_stats_moments, dim3(kStatMaxBlocks, njobs), dim3(kStatThreads), 0, st, ddesc);
+    hipLaunchKernelGGL(k_stats_entropy, dim3(kStatMaxBlocks, njobs), dim3(kStatThreads), 0, st, ddesc);
+    hipLaunchKernelGGL(k_stats_final, dim3((3 * njobs + 255) / 256), dim3(256), 0, st, ddesc, njobs);
     if (phases) hipEventRecord(phases->ev[3], st);
     return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
 }

@@ -154,6 +154,12 @@ class RQA:
               "rqa_get_timings")
         return {"prepare_ms": a.value, "tiles_ms": b.value, "stitch_ms": c.value}
 
+    def last_launch(self) -> dict:
+        """Waves per workgroup of the last run and whether it was a graph replay."""
+        w, g = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().rqa_last_launch(self._h, ctypes.byref(w), ctypes.byref(g)), "rqa_last_launch")
+        return {"waves": w.value, "graph_replay": bool(g.value)}
+
     def set_tiling(self, waves_per_group: int = 0, groups: int = 0):
         check(lib().rqa_set_tiling(self._h, int(waves_per_group), int(groups)), "rqa_set_tiling")
 
@@ -197,9 +203,9 @@ class RQA:
         n = self._nvec[0 if index is None else index] if self._nvec else 0
         ms = RqaMeasures()
         if histograms and n > 0:
-            d = np.zeros(n + 1, dtype=np.uint64)
-            v = np.zeros(n + 1, dtype=np.uint64)
-            w = np.zeros(n + 1, dtype=np.uint64)
+            d = np.empty(n + 1, dtype=np.uint64)   # filled completely by the library
+            v = np.empty(n + 1, dtype=np.uint64)
+            w = np.empty(n + 1, dtype=np.uint64)
             ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in (d, v, w)]
         else:
             d = v = w = None

@@ -94,3 +94,33 @@ def test_repeat_and_shape_independence(cuda):
         for a, b in zip(outs[0], o):
             same_hist(a, (b.diag, b.vert, b.white), "shape/repeat")
     comp.close()
+
+
+def test_graph_replays_match_eager(cuda):
+    """Identical repeated launches are replayed from a captured hipGraph (after the
+    autotuner has settled); every replay, with unrelated eager work and
+    synchronisations in between, equals the first eager result."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    s, p = workload("uniform", seed=4, n=80_000)
+    off, ln = windows_plan(len(s), 40, 500, 8000, seed=4)
+    ds = torch.from_numpy(s).to(cuda)
+    comp = RQA.from_params(p)
+    other = RQA(2, 1, 0.2, "euclidean")
+    ref = None
+    replays = 0
+    for rep in range(10):
+        _announce("graph", rep=rep)
+        comp.run_batch(ds, off, ln)
+        res = [comp.result_batch(w) for w in range(len(off))]
+        replays += comp.last_launch()["graph_replay"]
+        if ref is None:
+            ref = res
+        else:
+            for a, b in zip(ref, res):
+                same_hist(b, (a.diag, a.vert, a.white), f"replay {rep}")
+        other(ds[:5000])            # eager work on another handle between replays
+        torch.cuda.synchronize()
+    assert replays >= 4, "the repeated launch was never replayed from a graph"
+    comp.close()
+    other.close()
