@@ -7,7 +7,9 @@ Theiler window 1.  value = n_vec^2 recurrence-matrix cells per second (Gcells/s)
 with the series already resident in device memory.
 
 Also reported (outside the timed K steps):
-  roofline      live hipEvent time of the fused tile kernel vs the FP32 VALU peak
+  roofline      live hipEvent time of the fused tile kernel vs the FP32 vector peak
+                (78.6 T ops/s); traffic = HBM bytes per launch from the committed
+                FETCH_SIZE / WRITE_SIZE summary, null once the kernel changed
   cpu_baseline  the CPU oracle on a bounded sample of the same series
   batched       400 uneven sliding windows of uniform noise in one launch, vs the
                 same windows run one by one
@@ -34,8 +36,35 @@ if REPO not in sys.path:
 
 METRIC = "recurrence cells/s (Gcells/s) full RQA @N=1M, 1 GPU; batched p50/p99 latency"
 
-# FP32 VALU peak without FMA and without packed math: 256 CUs x 64 lanes x 2.4 GHz.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# FP32 vector peak in operations/s.  The published 157.3 TFLOP/s counts a fused
+# multiply-add as two flops: 256 CUs x 2.4 GHz x 128 FP32 lanes per clock per CU
+# x 2.  The predicate's operations (subtract, max, compare) are one operation per
+# lane each, so their peak is 256 x 2.4e9 x 128 = 78.6 T ops/s.
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+TILES_SRC = os.path.join(REPO, "paper_2402_16853_amd", "csrc", "rqa_tiles.hip")
+PMC_SUMMARY = os.path.join(REPO, "profiles", "k_tiles_lorenz_N1048576_pmc.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_tiles launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel source has changed since it was taken."""
+    import hashlib
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(TILES_SRC, "rb").read()).hexdigest()
+    if fields.get("kernel source sha256") != sha:
+        return None
+    try:
+        return int(fields["HBM bytes per launch"].replace(",", ""))
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -86,7 +115,7 @@ def bench_headline(args, torch, RQA, workload):
     comp = RQA.from_params(p)
     comp.set_profiling(True)
     if args.sweep:
-        for w in (4, 8, 16):
+        for w in (2, 4, 8):
             comp.set_tiling(w, 0)
             comp.run(ds)
             comp.result(histograms=False)
@@ -125,7 +154,8 @@ def bench_headline(args, torch, RQA, workload):
     log(f"[bench] {ms:.2f} ms/step  tiles {tile_ms:.2f} ms  stitch {np.mean(stitch):.2f} ms  "
         f"prepare {np.mean(prep):.2f} ms  RR={res.measures['rr']:.6f} DET={res.measures['det']:.6f}")
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": measured_traffic(),
             "kernel": "k_tiles<Linf,m=3>", "kernel_ms": round(tile_ms, 3),
             "ops_per_launch": ops,
             "stitch_ms": round(float(np.mean(stitch)), 3),
@@ -254,6 +284,29 @@ def bench_served(args, torch, RQA, Server, served_requests):
             "sequential_gcells_per_s": round(cells / ts / 1e9, 3)}
 
 
+def probe_valu():
+    """Sustained issue rate of the predicate loop alone (16 columns per trip:
+    96 predicate VALU instructions + 1 bookkeeping), as wave-instructions per
+    clock per CU at 2.4 GHz and as FP32 algorithmic ops/s (6 per column-lane)."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(REPO, "paper_2402_16853_amd", "libcalib.so"))
+    lib.calib_predicate.restype = ctypes.c_int
+    lib.calib_predicate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_double)]
+    iters = 4000
+    for blocks, threads in ((256, 512), (512, 512), (768, 512), (1024, 512), (1024, 256),
+                            (2048, 256)):
+        ms = ctypes.c_double()
+        rc = lib.calib_predicate(blocks, threads, iters, ctypes.byref(ms))
+        waves = blocks * threads // 64
+        instr = waves * iters * 97.0
+        rate = instr / (ms.value * 1e-3) / 256 / 2.4e9
+        ops = waves * iters * 16 * 6 * 64 / (ms.value * 1e-3) / 1e12
+        print(json.dumps({"probe": "valu", "blocks": blocks, "threads": threads, "rc": rc,
+                          "ms": round(ms.value, 3), "valu_per_clk_per_cu_at_2.4GHz": round(rate, 3),
+                          "predicate_tops": round(ops, 3)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +323,9 @@ def main():
                     "headline: batched, served, cpu (default: all)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = default)")
     ap.add_argument("--sweep", action="store_true", help="time the tile kernel per waves setting")
+    ap.add_argument("--probe-valu", action="store_true",
+                    help="only measure the issue rate of the predicate's VALU instruction "
+                         "stream (libcalib.so) and exit")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -283,6 +339,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.probe_valu:
+        probe_valu()
+        return
     if args.probe_copy:
         n = args.probe_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")

@@ -135,7 +135,7 @@ int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert,
                            const uint64_t *white, int64_t n, const rqa_params *p,
                            rqa_measures *out);
 
-/* Tile-shape override: waves per workgroup (1..16, rows per strip = 64*waves;
+/* Tile-shape override: waves per workgroup (1..8, rows per strip = 64*waves;
  * 0 = chosen by the built-in autotuner, which times the candidate shapes on the
  * first runs of each launch signature; RQA_AUTOTUNE_CACHE=<file> persists its
  * choices) and workgroups per launch (0 = fill the device).  Results never

@@ -32,8 +32,23 @@ COMMON = [
 ]
 
 
+CALIB_SRC = "calib.hip"
+CALIB_LIB = os.path.join(HERE, "libcalib.so")
+
+
+def build_calib(verbose: bool = False) -> str:
+    """libcalib.so: the VALU-rate calibration kernel used by bench.py --probe-valu."""
+    tmp = CALIB_LIB + ".tmp"
+    cmd = [HIPCC, "-x", "hip", *COMMON, "-shared", os.path.join(CSRC, CALIB_SRC), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, CALIB_LIB)
+    return CALIB_LIB
+
+
 def build(verbose: bool = False, save_temps: str | None = None) -> str:
-    """Compile every source and link librqa.so; always rebuilds."""
+    """Compile every source and link librqa.so (and libcalib.so); always rebuilds."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
@@ -55,6 +70,7 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True, cwd=objdir)
     os.replace(tmp, LIB)
+    build_calib(verbose)
     return LIB
 
 

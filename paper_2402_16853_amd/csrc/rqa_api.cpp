@@ -83,8 +83,8 @@ using namespace rqa;
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kCandidates[] = {2, 4, 8, 16};
-constexpr int kNumCandidates = 4;
+constexpr int kCandidates[] = {2, 4, 8};
+constexpr int kNumCandidates = 3;
 
 struct TuneEntry {
     int next = 0;          // next candidate to try
@@ -106,7 +106,7 @@ void tune_load_locked() {
     std::string key;
     int waves;
     while (f >> key >> waves) {
-        if (waves < 1 || waves > 16) continue;
+        if (waves < 1 || waves > 8) continue;
         TuneEntry &e = g_tune[key];
         e.best = waves;
         e.done = true;
@@ -513,7 +513,7 @@ int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uin
 }
 
 int rqa_set_tiling(rqa_handle *h, int32_t waves_per_group, int32_t groups) {
-    if (!h || waves_per_group < 0 || waves_per_group > 16 || groups < 0) return RQA_EINVAL;
+    if (!h || waves_per_group < 0 || waves_per_group > 8 || groups < 0) return RQA_EINVAL;
     h->waves = waves_per_group;
     h->groups = groups;
     return RQA_OK;

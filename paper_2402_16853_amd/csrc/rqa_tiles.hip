@@ -56,10 +56,10 @@ KParams make_kparams(const rqa_params &p) {
 
 namespace {
 
-constexpr int kMaxWaves = 16;
+constexpr int kMaxWaves = 8;
 constexpr int kCapD = 1024;    // LDS bins for diagonal lengths < kCapD
 constexpr int kCapV = 1024;    // LDS bins for vertical lengths < kCapV
-constexpr int kCapW = 6144;    // LDS bins for white-vertical lengths < kCapW
+constexpr int kCapW = 6016;    // LDS bins for white-vertical lengths < kCapW
 constexpr int kMaxM = 6;       // embedding dimensions held in registers
 constexpr int kStitchThreads = 256;
 constexpr int kStatThreads = 256;
@@ -396,16 +396,27 @@ __global__ void k_reset(const JobDesc *__restrict__ jobs, int njobs, int *counte
 // Kernel 2: the fused tile pass.  Persistent workgroups pull (job, strip) work
 // items of one (norm, m) group from a counter.
 // ---------------------------------------------------------------------------
+// LDS of a tile workgroup (dynamic shared memory): privatised histogram bins,
+// the double-buffered carry slots between consecutive waves (vertical and
+// diagonal states, one u32 per lane), and the current work item.  Sized for
+// the launch's wave count (40 KB for 8 waves).  The kernel is compiled for six
+// waves per SIMD (at most 80 VGPRs, no spills), i.e. three 8-wave workgroups
+// per CU; the LDS would allow four.
 struct StripLds {
-    uint32_t bd[kCapD];
-    uint32_t bv[kCapV];
-    uint32_t bw[kCapW];
-    uint32_t vslot[2][kMaxWaves][64];
-    uint32_t dslot[2][kMaxWaves][64];
-    int item;
+    uint32_t *bd, *bv, *bw;
+    uint32_t *vslot;    // [2][waves][64]
+    uint32_t *dslot;    // [2][waves][64]
+    int *item;
+    int nw;
+    __device__ uint32_t &vs(int buf, int w, int lane) { return vslot[(buf * nw + w) * 64 + lane]; }
+    __device__ uint32_t &ds(int buf, int w, int lane) { return dslot[(buf * nw + w) * 64 + lane]; }
 };
 
-__device__ void flush_bins(StripLds &L, const JobDesc &j) {
+__host__ __device__ constexpr size_t strip_lds_bytes(int waves) {
+    return sizeof(uint32_t) * ((size_t)kCapD + kCapV + kCapW + 2 * 2 * (size_t)waves * 64) + 16;
+}
+
+__device__ void flush_bins(const StripLds &L, const JobDesc &j) {
     const int hl = j.n + 1;
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
         if (t < kCapD) {
@@ -423,6 +434,7 @@ __device__ void flush_bins(StripLds &L, const JobDesc &j) {
 
 template <int NORM, int M>
 __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
+    static_assert(kMaxWaves <= 8, "LDS budget assumes at most 8 waves per workgroup");
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int nw = blockDim.x >> 6;
@@ -444,6 +456,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
     for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? rowp[(int64_t)k * tau] : 0.0f;
 
     Bins bins{L.bd, L.bv, L.bw};
+    const LineCtx hctx{&j, bins, 0, false, (uint32_t)i};
     Run hs{0, 0, 0};          // horizontal run of this lane's row
     bool hstarted = false;
     Run left{0, 0, 0};        // diagonal carry from the previous tile (upper part end)
@@ -477,17 +490,82 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                 xhi = (uint32_t)(X >> 32);
             }
 
+            const bool any = __ballot(X != 0ull) != 0ull;
+
+            if (interior && !any) {
+                // No recurrence in an interior tile: every open run sees 64
+                // white cells.  Only carried states change; a black run that
+                // was open ends at the tile's first cell.
+                if (hs.color) {
+                    finish_run<kHoriz>(hctx, 1u, hs.len, hs.first);
+                    hs = Run{0u, 64u, 0u};
+                } else {
+                    hs.len += 64u;
+                }
+                {
+                    Run st = wave == 0 ? Run{0u, 0u, 1u} : unpack_run(L.vs((step - 1) & 1, wave - 1, lane));
+                    const int64_t sidx = soff + (jbase + lane - R0 - wp);
+                    if (st.color) {
+                        const LineCtx lc{&j, bins, sidx, true, 0u};
+                        finish_run<kVert>(lc, 1u, st.len, st.first);
+                        st = Run{0u, 64u, 0u};
+                    } else {
+                        st.len += 64u;
+                    }
+                    if (wave == nw - 1) {
+                        const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
+                        j.vlast[sidx] = pk;
+                        if (st.first) j.vfirst[sidx] = pk;
+                    } else {
+                        L.vs(step & 1, wave, lane) = pack_run(st);
+                    }
+                }
+                {
+                    // Interior: both diagonal parts of every lane are valid and
+                    // continue on the next row.
+                    const int kup = jbase + lane - R;
+                    const int klo = kup - 64;
+                    Run up;
+                    if (wave == 0) {
+                        j.dfirst[soff + (kup - wp)] = 0;   // white first cell
+                        up = Run{0u, 0u, 0u};
+                    } else {
+                        up = unpack_run(L.ds((step - 1) & 1, wave - 1, lane));
+                    }
+                    if (up.color) {
+                        const LineCtx lc{&j, bins, soff + (kup - wp), true, 0u};
+                        finish_run<kDiag>(lc, 1u, up.len, up.first);
+                        up = Run{0u, 0u, 0u};
+                    }
+                    // Lane 0's lower part is empty (its diagonal left this wave
+                    // at the previous tile's corner): its run goes on unchanged.
+                    Run lw = left;
+                    if (lw.color && lane != 0) {
+                        const LineCtx lc{&j, bins, soff + (klo - wp), true, 0u};
+                        finish_run<kDiag>(lc, 1u, lw.len, lw.first);
+                        lw = Run{0u, 0u, 0u};
+                    }
+                    if (wave < nw - 1) {
+                        L.ds(step & 1, wave, lane) = pack_run(lw);
+                    } else {
+                        const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
+                        j.dlast[soff + (klo - wp)] = b;
+                        if (lw.first) j.dfirst[soff + (klo - wp)] = b;
+                    }
+                    left = up;
+                }
+                __syncthreads();
+                continue;
+            }
+
             // ---- horizontal runs (row i of U) ----
             if (lo_v < hi_v) {
                 if (!hstarted) {
                     hstarted = true;
                     hs = Run{(uint32_t)((X >> lo_v) & 1ull), 0u, 1u};
                 }
-                LineCtx lc{&j, bins, 0, false, (uint32_t)i};
-                run_segment<kHoriz>(X, vmask, (uint32_t)lo_v, (uint32_t)hi_v, hs, lc);
+                run_segment<kHoriz>(X, vmask, (uint32_t)lo_v, (uint32_t)hi_v, hs, hctx);
             }
-
-            const bool any = __ballot(X != 0ull) != 0ull;
 
             // ---- vertical runs (columns of U) ----
             {
@@ -501,7 +579,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                     const uint32_t vhi = e >= 63 ? 64u : (uint32_t)(e + 1);
                     Run st;
                     if (wave == 0) st = Run{(uint32_t)(Y & 1ull), 0u, 1u};
-                    else st = unpack_run(L.vslot[(step - 1) & 1][wave - 1][lane]);
+                    else st = unpack_run(L.vs((step - 1) & 1, wave - 1, lane));
                     const int64_t sidx = soff + (jc - R0 - wp);
                     LineCtx lc{&j, bins, sidx, true, 0u};
                     const uint64_t vwin = vhi >= 64 ? ~0ull : ((1ull << vhi) - 1ull);
@@ -511,7 +589,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                         j.vlast[sidx] = pk;
                         if (st.first) j.vfirst[sidx] = pk;
                     } else {
-                        L.vslot[step & 1][wave][lane] = pack_run(st);
+                        L.vs(step & 1, wave, lane) = pack_run(st);
                     }
                 }
             }
@@ -545,7 +623,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                 } else if (jbase + q > n - 1) {
                     up = Run{0u, 0u, 0u};   // starts past the border
                 } else {
-                    up = unpack_run(L.dslot[(step - 1) & 1][wave - 1][lane]);
+                    up = unpack_run(L.ds((step - 1) & 1, wave - 1, lane));
                 }
                 {
                     const bool ok = kup >= wp && kup <= n - 1 - R0;
@@ -563,7 +641,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                     if (R + 64 + klo > n - 1) {
                         if (lw.color || lw.first) finish_run<kDiag>(lc, lw.color, lw.len, lw.first);
                     } else if (wave < nw - 1) {
-                        L.dslot[step & 1][wave][lane] = pack_run(lw);
+                        L.ds(step & 1, wave, lane) = pack_run(lw);
                     } else if (ok) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
                         j.dlast[soff + (klo - wp)] = b;
@@ -578,10 +656,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
 
     if (wave_has_u) {
         // Rows end at column n-1: their last run is complete.
-        if (hstarted) {
-            LineCtx lc{&j, bins, 0, false, (uint32_t)i};
-            finish_run<kHoriz>(lc, hs.color, hs.len, hs.first);
-        }
+        if (hstarted) finish_run<kHoriz>(hctx, hs.color, hs.len, hs.first);
         // Upper parts that left the last tile on its right edge end at the border.
         const int kup = j.c_last * 64 + lane - R;
         const bool ok = kup >= wp && kup <= n - 1 - R0;
@@ -591,10 +666,19 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
 }
 
 template <int NORM, int M>
-__global__ void __launch_bounds__(1024) k_tiles(const JobDesc *__restrict__ jobs,
-                                                const GroupDesc *__restrict__ groups, int g,
-                                                int *counters) {
-    __shared__ StripLds L;
+__global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
+k_tiles(const JobDesc *__restrict__ jobs, const GroupDesc *__restrict__ groups, int g,
+        int *counters) {
+    extern __shared__ uint32_t lds_words[];
+    const int nw = blockDim.x >> 6;
+    StripLds L;
+    L.bd = lds_words;
+    L.bv = L.bd + kCapD;
+    L.bw = L.bv + kCapV;
+    L.vslot = L.bw + kCapW;
+    L.dslot = L.vslot + 2 * nw * 64;
+    L.item = reinterpret_cast<int *>(L.dslot + 2 * nw * 64);
+    L.nw = nw;
     const GroupDesc gd = groups[g];
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
         if (t < kCapD) L.bd[t] = 0;
@@ -603,9 +687,9 @@ __global__ void __launch_bounds__(1024) k_tiles(const JobDesc *__restrict__ jobs
     }
     __syncthreads();
     while (true) {
-        if (threadIdx.x == 0) L.item = atomicAdd(counters + g, 1);
+        if (threadIdx.x == 0) *L.item = atomicAdd(counters + g, 1);
         __syncthreads();
-        const int item = L.item;
+        const int item = *L.item;
         __syncthreads();
         if (item >= gd.items) break;
         // locate the job: largest job index in [job0, job1) with strip_base <= item
@@ -1052,7 +1136,8 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         const int w = jobs_in[order[gd.job0]].waves;
         TileKernel kern = tile_kernel(kp.norm, kp.m);
         int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, 0) != hipSuccess ||
+        const size_t lds = strip_lds_bytes(w);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, lds) != hipSuccess ||
             occ < 1)
             occ = 1;
         int grid = groups_req > 0 ? groups_req : ncu * occ;
@@ -1065,7 +1150,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
             if (!used[k]) hipStreamWaitEvent(gs, aux->fork, 0);
             used[k] = true;
         }
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), 0, gs, ddesc, dgroups, g, dcounters);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * w), lds, gs, ddesc, dgroups, g, dcounters);
         ++launched;
     }
     if (fork) {

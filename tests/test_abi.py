@@ -70,7 +70,7 @@ def test_handle_lifecycle_and_host_errors():
     assert L.rqa_result(h, ctypes.byref(ms), None, None, None, 0) == -7   # no run yet
     assert L.rqa_run(h, None, 100, None) == -1                   # null series
     assert L.rqa_run_batch(h, None, 100, None, None, 0, None) == -1
-    assert L.rqa_set_tiling(h, 17, 0) == -1
+    assert L.rqa_set_tiling(h, 9, 0) == -1
     assert L.rqa_set_tiling(h, 4, 0) == 0
     L.rqa_destroy(h)
     L.rqa_destroy(None)

@@ -8,7 +8,7 @@ shapes.  Each case prints its parameters before touching the GPU.
 import numpy as np
 import pytest
 
-from workloads import Params, workload
+from workloads import Params, corner_lines, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -79,7 +79,7 @@ def test_random_small(seed, cuda, oracle_lib):
         assert_same(res, *ref, tag=f"seed {seed} waves {waves}")
 
 
-@pytest.mark.parametrize("waves", [1, 2, 3, 8, 16])
+@pytest.mark.parametrize("waves", [1, 2, 3, 5, 8])
 def test_tile_shapes(waves, cuda, oracle_lib):
     """The result does not depend on the workgroup shape or count."""
     s, p = workload("logistic", seed=3, n=3_333)
@@ -116,3 +116,16 @@ def test_ar1_config(cuda, oracle_lib):
     ref = oracle_lib.rqa(s, p)
     _announce("ar1_season", n=len(s))
     assert_same(run_gpu(s, p, cuda), *ref, tag="ar1_season")
+
+
+@pytest.mark.parametrize("waves", [1, 2, 3, 4, 8])
+def test_lines_through_empty_tile_corners(waves, cuda, oracle_lib):
+    """Isolated diagonal lines crossing from row 64q-1 to row 64q at a tile corner,
+    next to tiles with no recurrence at all: runs carried across wave and strip
+    boundaries through empty tiles."""
+    s = corner_lines(8, 20)
+    for norm, m in ((1, 1), (3, 1), (2, 2)):
+        p = Params(m=m, tau=1, eps=0.25, norm=norm, theiler=1)
+        _announce("corner_lines", waves=waves, norm=norm, m=m, n=len(s))
+        assert_same(run_gpu(s, p, cuda, waves=waves), *oracle_lib.rqa(s, p),
+                    tag=f"corner lines waves {waves} norm {norm} m {m}")

@@ -10,7 +10,9 @@
 * invariants: first moments of the histograms equal the number of recurrence
   points counted directly, total column length is n^2, diagonal bins are even,
   s -> -s and power-of-two rescaling leave the histograms unchanged;
-* the m = 1 special case, where L1 and L-infinity reduce to |s_i - s_j| <= eps.
+* the m = 1 special case, where L1 and L-infinity reduce to |s_i - s_j| <= eps;
+* isolated copied segments: a known set of diagonal lines and the column runs
+  they cut, written out cell by cell.
 """
 import itertools
 import math
@@ -20,6 +22,7 @@ import pytest
 
 import oracle
 from oracle import brute
+from workloads import corner_lines
 
 
 def hist(s, m, tau, eps, norm, w):
@@ -181,3 +184,32 @@ def test_rejects_bad_arguments():
         oracle.histograms(s, 1, 1, -1.0, 1, 1)    # negative radius
     with pytest.raises(ValueError):
         oracle.histograms(s, 1, 1, 0.1, 4, 1)     # unknown norm
+
+
+@pytest.mark.parametrize("boundaries,half,norm", [(2, 20, 1), (8, 20, 3), (5, 7, 2)])
+def test_copied_segments_closed_form(boundaries, half, norm):
+    """Each copied segment of length 2*half is one diagonal line (counted in both
+    triangles); every black cell sits alone in its column, cutting it into two
+    white runs; all other columns are white from end to end."""
+    s = corner_lines(boundaries, half)
+    n = len(s)
+    d, v, wh = hist(s, 1, 1, 0.25, norm, 1)
+    D = np.zeros(n + 1, dtype=np.uint64)
+    V = np.zeros(n + 1, dtype=np.uint64)
+    W = np.zeros(n + 1, dtype=np.uint64)
+    D[2 * half] = 2 * boundaries
+    black_rows = {}
+    for q in range(1, boundaries + 1):
+        r0, k = 64 * q, 1024 + 128 * q
+        for r in range(r0 - half, r0 + half):
+            black_rows[r + k] = r          # upper triangle: column r+k, row r
+            black_rows[r] = r + k          # lower triangle: column r, row r+k
+    V[1] = len(black_rows)
+    for col in range(n):
+        if col in black_rows:
+            i = black_rows[col]
+            W[i] += 1
+            W[n - 1 - i] += 1
+        else:
+            W[n] += 1
+    assert np.array_equal(d, D) and np.array_equal(v, V) and np.array_equal(wh, W)

@@ -120,6 +120,22 @@ def sine_series(n: int = 1_000_001, cycles_pi: float = 1000.0) -> np.ndarray:
     return _f32(np.sin(np.linspace(0.0, cycles_pi * math.pi, n)))
 
 
+def corner_lines(boundaries: int = 8, half: int = 20) -> np.ndarray:
+    """Strictly increasing series with copied segments: for q = 1..boundaries the
+    values s[64q-half : 64q+half] reappear shifted by k_q = 1024 + 128 q.  With
+    m = 1 and eps < 1 the only recurrences are these copies, so the matrix holds
+    exactly one diagonal line of length 2*half per q (and its mirror image),
+    passing from row 64q-1 to row 64q, i.e. through the corner shared by four
+    64x64 tiles, with empty tiles on either side.  A structural test input for
+    runs that cross tile, wave and strip boundaries."""
+    n = 1024 + 192 * (boundaries + 1) + 64
+    s = np.arange(n, dtype=np.float64)
+    for q in range(1, boundaries + 1):
+        r0, k = 64 * q, 1024 + 128 * q
+        s[r0 - half + k:r0 + half + k] = s[r0 - half:r0 + half]
+    return _f32(s)
+
+
 def population_std_fp64(series: np.ndarray) -> float:
     """Population standard deviation (ddof=0) accumulated in FP64."""
     return float(np.asarray(series, dtype=np.float64).std())
