@@ -8,6 +8,9 @@ it.  It shares no code with the HIP implementation.
   in C, compiled with ``gcc -O2 -ffp-contract=off`` (``rqa_oracle.c``).
 * ``measures``   -- RR, DET, L, Lmax, DIV, L_entr, LAM, TT, Vmax, V_entr, W,
   Wmax, W_entr (names of Tab. 3) in FP64 from the histograms.
+* ``cross_histograms`` / ``cross_measures`` -- cross recurrence of two series
+  (rows: series a, columns: series b; 2N-1 diagonals, each run once).
+* ``matrix_histograms`` -- the same histograms of a given bit matrix.
 * ``brute``      -- an independent pure-Python brute force that materialises the
   whole matrix for tiny inputs; it pins the C code.
 """
@@ -55,6 +58,19 @@ def _load():
         lib.rqa_oracle_measures.argtypes = [
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.rqa_oracle_cross_histograms.restype = ctypes.c_int
+        lib.rqa_oracle_cross_histograms.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+            ctypes.c_int, ctypes.c_float, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.rqa_oracle_matrix_histograms.restype = ctypes.c_int
+        lib.rqa_oracle_matrix_histograms.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.rqa_oracle_rect_measures.restype = ctypes.c_int
+        lib.rqa_oracle_rect_measures.argtypes = [
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         lib.rqa_oracle_n_vectors.restype = ctypes.c_int64
         lib.rqa_oracle_n_vectors.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int]
         _lib = lib
@@ -103,3 +119,64 @@ def rqa(series, params, threads: int = 0):
     d, v, w = histograms(series, params.m, params.tau, params.eps, params.norm, params.theiler,
                          threads)
     return (d, v, w), measures(d, v, w, params.theiler, params.lmin, params.vmin, params.wmin)
+
+
+def cross_histograms(a, b, m: int, tau: int, eps: float, norm: int, theiler: int = 0,
+                     threads: int = 0):
+    """Histograms of the cross recurrence matrix of series a (rows) and b
+    (columns): three uint64 arrays of length max(n_a, n_b)+1."""
+    sa = np.ascontiguousarray(a, dtype=np.float32)
+    sb = np.ascontiguousarray(b, dtype=np.float32)
+    na, nb = n_vectors(len(sa), m, tau), n_vectors(len(sb), m, tau)
+    if na < 1 or nb < 1:
+        raise ValueError("series too short for the embedding")
+    L = max(na, nb) + 1
+    d, v, w = (np.zeros(L, dtype=np.uint64) for _ in range(3))
+    rc = _load().rqa_oracle_cross_histograms(sa.ctypes.data, len(sa), sb.ctypes.data, len(sb),
+                                             m, tau, float(np.float32(eps)), norm, theiler,
+                                             d.ctypes.data, v.ctypes.data, w.ctypes.data,
+                                             threads)
+    if rc != 0:
+        raise ValueError("invalid oracle arguments")
+    return d, v, w
+
+
+def matrix_histograms(bits, n_rows: int, n_cols: int, theiler: int = 0, threads: int = 0):
+    """Histograms of a given bit matrix: ``bits`` is a uint64 array of shape
+    (n_rows, words) with bit b of word c of row i = column 64c+b."""
+    B = np.ascontiguousarray(bits, dtype=np.uint64)
+    if B.ndim != 2 or B.shape[0] != n_rows:
+        raise ValueError("bits must have shape (n_rows, words)")
+    L = max(n_rows, n_cols) + 1
+    d, v, w = (np.zeros(L, dtype=np.uint64) for _ in range(3))
+    rc = _load().rqa_oracle_matrix_histograms(B.ctypes.data, n_rows, n_cols, B.shape[1], theiler,
+                                              d.ctypes.data, v.ctypes.data, w.ctypes.data,
+                                              threads)
+    if rc != 0:
+        raise ValueError("invalid oracle arguments")
+    return d, v, w
+
+
+def rect_measures(diag, vert, white, n_rows: int, n_cols: int, theiler: int, lmin: int,
+                  vmin: int, wmin: int) -> dict:
+    """Measures of an n_rows x n_cols matrix (cross recurrence or a given
+    matrix); ``n_vec`` reports n_rows."""
+    d = np.ascontiguousarray(diag, dtype=np.uint64)
+    v = np.ascontiguousarray(vert, dtype=np.uint64)
+    w = np.ascontiguousarray(white, dtype=np.uint64)
+    out = np.zeros(len(MEASURE_NAMES), dtype=np.float64)
+    rc = _load().rqa_oracle_rect_measures(d.ctypes.data, v.ctypes.data, w.ctypes.data, n_rows,
+                                          n_cols, theiler, lmin, vmin, wmin, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("invalid histogram arguments")
+    return dict(zip(MEASURE_NAMES, out.tolist()))
+
+
+def cross_rqa(a, b, params, threads: int = 0):
+    """Cross recurrence histograms and measures for a parameter object."""
+    d, v, w = cross_histograms(a, b, params.m, params.tau, params.eps, params.norm,
+                               params.theiler, threads)
+    na = n_vectors(len(a), params.m, params.tau)
+    nb = n_vectors(len(b), params.m, params.tau)
+    return (d, v, w), rect_measures(d, v, w, na, nb, params.theiler, params.lmin, params.vmin,
+                                    params.wmin)

@@ -68,23 +68,63 @@ def _runs(seq, value):
     return out
 
 
+def cross_matrix(a, b, m, tau, eps, norm, theiler=0):
+    """The masked cross recurrence matrix (rows: vectors of a, columns: vectors of
+    b) as a list of lists of 0/1 ints."""
+    sa = [F32(v) for v in np.asarray(a, dtype=np.float32).tolist()]
+    sb = [F32(v) for v in np.asarray(b, dtype=np.float32).tolist()]
+    na = len(sa) - (m - 1) * tau
+    nb = len(sb) - (m - 1) * tau
+    va = [[sa[i + k * tau] for k in range(m)] for i in range(na)]
+    vb = [[sb[j + k * tau] for k in range(m)] for j in range(nb)]
+    e = F32(eps)
+    e2 = F32(e * e)
+    R = [[0] * nb for _ in range(na)]
+    for i in range(na):
+        for j in range(nb):
+            if abs(i - j) < theiler:
+                continue
+            R[i][j] = 1 if _dist_leq(va[i], vb[j], norm, e, e2) else 0
+    return R
+
+
 def histograms_from_matrix(R):
-    n = len(R)
-    diag = np.zeros(n + 1, dtype=np.uint64)
-    vert = np.zeros(n + 1, dtype=np.uint64)
-    white = np.zeros(n + 1, dtype=np.uint64)
-    for k in range(-(n - 1), n):
-        line = [R[i][i + k] for i in range(n) if 0 <= i + k < n]
-        for L in _runs(line, 1):
-            diag[L] += 1
-    for j in range(n):
-        col = [R[i][j] for i in range(n)]
-        for L in _runs(col, 1):
-            vert[L] += 1
-        for L in _runs(col, 0):
-            white[L] += 1
+    """Histograms of a rectangular 0/1 matrix (list of rows): every diagonal,
+    every column; arrays of length max(rows, cols)+1."""
+    nr, nc = len(R), len(R[0])
+    L = max(nr, nc) + 1
+    diag = np.zeros(L, dtype=np.uint64)
+    vert = np.zeros(L, dtype=np.uint64)
+    white = np.zeros(L, dtype=np.uint64)
+    for k in range(-(nr - 1), nc):
+        line = [R[i][i + k] for i in range(nr) if 0 <= i + k < nc]
+        for run in _runs(line, 1):
+            diag[run] += 1
+    for j in range(nc):
+        col = [R[i][j] for i in range(nr)]
+        for run in _runs(col, 1):
+            vert[run] += 1
+        for run in _runs(col, 0):
+            white[run] += 1
     return diag, vert, white
 
 
 def histograms(series, m, tau, eps, norm, theiler):
     return histograms_from_matrix(matrix(series, m, tau, eps, norm, theiler))
+
+
+def cross_histograms(a, b, m, tau, eps, norm, theiler=0):
+    return histograms_from_matrix(cross_matrix(a, b, m, tau, eps, norm, theiler))
+
+
+def pack_rows(R):
+    """Bit-pack a 0/1 matrix row-major into uint64 words (bit b of word c of row
+    i = column 64c+b)."""
+    nr, nc = len(R), len(R[0])
+    words = (nc + 63) // 64
+    out = np.zeros((nr, words), dtype=np.uint64)
+    for i in range(nr):
+        for j in range(nc):
+            if R[i][j]:
+                out[i, j >> 6] |= np.uint64(1) << np.uint64(j & 63)
+    return out

@@ -32,6 +32,16 @@
  * walks every column j over all rows i = 0..n-1 and evaluates the predicate
  * for every cell, the way a sequential on-the-fly tool would.  Memory is O(n).
  *
+ * Cross recurrence (the cRQA discussion of the related work, and Sect. 4.2,
+ * where a non-symmetric matrix has 2N-1 diagonals): rows are the delay vectors
+ * of a series a, columns those of a series b, same m, tau, norm and radius; the
+ * matrix is n_a x n_b and not symmetric, so every diagonal k = j - i from
+ * -(n_a-1) to n_b-1 is walked and each run counted once; columns run over all
+ * n_a rows.  The optional Theiler window masks |i-j| < w by index.
+ *
+ * Given matrix: the same three histograms of a caller-supplied bit matrix
+ * (row-major, bit b of 64-bit word c of row i = column 64c+b).
+ *
  * Build: gcc -O2 -ffp-contract=off (no -ffast-math); FP32 denormals are kept.
  * Measures (Sect. 8.1, Tab. 3 names; definitions are the standard ones) are
  * computed in FP64 from the integer histograms.
@@ -189,10 +199,213 @@ int rqa_oracle_histograms(const float *s, int64_t n_points, int m, int tau, floa
     return 0;
 }
 
+/* Predicate for row vector i of series a and column vector j of series b, the
+ * same operation sequence as oracle_recurrent with s[i + k tau] taken from a and
+ * s[j + k tau] from b. */
+static int oracle_cross_recurrent(const float *a, int64_t i, const float *b, int64_t j, int m,
+                                  int tau, int norm, float eps, float eps_sq)
+{
+    int k;
+    if (norm == ORACLE_L1) {
+        float acc = fabsf(a[i] - b[j]);
+        for (k = 1; k < m; ++k) {
+            float d = a[i + (int64_t)k * tau] - b[j + (int64_t)k * tau];
+            acc = acc + fabsf(d);
+        }
+        return acc <= eps;
+    }
+    if (norm == ORACLE_L2) {
+        float d = a[i] - b[j];
+        float acc = d * d;
+        for (k = 1; k < m; ++k) {
+            float e = a[i + (int64_t)k * tau] - b[j + (int64_t)k * tau];
+            float sq = e * e;
+            acc = acc + sq;
+        }
+        return acc <= eps_sq;
+    }
+    {
+        float acc = fabsf(a[i] - b[j]);
+        for (k = 1; k < m; ++k) {
+            float t = fabsf(a[i + (int64_t)k * tau] - b[j + (int64_t)k * tau]);
+            if (t > acc)
+                acc = t;
+        }
+        return acc <= eps;
+    }
+}
+
+/* Cell (i, j) of one of the two non-symmetric matrices: the cross recurrence
+ * matrix of (a, b), or a given bit matrix. */
+typedef struct {
+    const float *a, *b;
+    int m, tau, norm;
+    float eps, eps_sq;
+    const uint64_t *bits;   /* non-NULL: given matrix */
+    int64_t words;          /* 64-bit words per row of the given matrix */
+    int64_t w;              /* Theiler window */
+} oracle_rect;
+
+static int oracle_rect_cell(const oracle_rect *r, int64_t i, int64_t j)
+{
+    int64_t gap = i > j ? i - j : j - i;
+    if (gap < r->w)
+        return 0;
+    if (r->bits)
+        return (int)((r->bits[i * r->words + (j >> 6)] >> (j & 63)) & 1u);
+    return oracle_cross_recurrent(r->a, i, r->b, j, r->m, r->tau, r->norm, r->eps, r->eps_sq);
+}
+
+/* Lines of an n_rows x n_cols matrix: every diagonal k = j - i once, every
+ * column over all rows.  Histograms hold max(n_rows, n_cols)+1 entries. */
+static void oracle_rect_histograms(const oracle_rect *r, int64_t n_rows, int64_t n_cols,
+                                   uint64_t *diag, uint64_t *vert, uint64_t *white, int nt)
+{
+    int64_t len = (n_rows > n_cols ? n_rows : n_cols) + 1, k, j;
+    memset(diag, 0, sizeof(uint64_t) * (size_t)len);
+    memset(vert, 0, sizeof(uint64_t) * (size_t)len);
+    memset(white, 0, sizeof(uint64_t) * (size_t)len);
+#pragma omp parallel num_threads(nt)
+    {
+        uint64_t *ld = (uint64_t *)calloc((size_t)len, sizeof(uint64_t));
+        uint64_t *lv = (uint64_t *)calloc((size_t)len, sizeof(uint64_t));
+        uint64_t *lw = (uint64_t *)calloc((size_t)len, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 16)
+        for (k = -(n_rows - 1); k < n_cols; ++k) {
+            int64_t run = 0, t = k < 0 ? -k : 0;
+            for (; t < n_rows && t + k < n_cols; ++t) {
+                if (oracle_rect_cell(r, t, t + k)) {
+                    run += 1;
+                } else if (run > 0) {
+                    ld[run] += 1;
+                    run = 0;
+                }
+            }
+            if (run > 0)
+                ld[run] += 1;
+        }
+#pragma omp for schedule(dynamic, 16)
+        for (j = 0; j < n_cols; ++j) {
+            int64_t black = 0, blank = 0, i;
+            for (i = 0; i < n_rows; ++i) {
+                if (oracle_rect_cell(r, i, j)) {
+                    if (blank > 0) {
+                        lw[blank] += 1;
+                        blank = 0;
+                    }
+                    black += 1;
+                } else {
+                    if (black > 0) {
+                        lv[black] += 1;
+                        black = 0;
+                    }
+                    blank += 1;
+                }
+            }
+            if (black > 0)
+                lv[black] += 1;
+            if (blank > 0)
+                lw[blank] += 1;
+        }
+#pragma omp critical
+        {
+            int64_t l;
+            for (l = 0; l < len; ++l) {
+                diag[l] += ld[l];
+                vert[l] += lv[l];
+                white[l] += lw[l];
+            }
+        }
+        free(ld);
+        free(lv);
+        free(lw);
+    }
+}
+
+static int oracle_threads(int threads)
+{
+#ifdef _OPENMP
+    return threads > 0 ? threads : omp_get_max_threads();
+#else
+    (void)threads;
+    return 1;
+#endif
+}
+
+/* Cross recurrence histograms of series a (rows) against series b (columns);
+ * each array holds max(n_a, n_b)+1 entries.  Returns 0, or -1 for invalid
+ * arguments. */
+int rqa_oracle_cross_histograms(const float *a, int64_t na_points, const float *b,
+                                int64_t nb_points, int m, int tau, float eps, int norm,
+                                int theiler, uint64_t *diag, uint64_t *vert, uint64_t *white,
+                                int threads)
+{
+    oracle_rect r;
+    int64_t na, nb;
+    if (!a || !b || !diag || !vert || !white || m < 1 || tau < 1 || theiler < 0 ||
+        norm < 1 || norm > 3 || !(eps >= 0.0f) || isinf(eps))
+        return -1;
+    na = rqa_oracle_n_vectors(na_points, m, tau);
+    nb = rqa_oracle_n_vectors(nb_points, m, tau);
+    if (na < 1 || nb < 1)
+        return -1;
+    r.a = a;
+    r.b = b;
+    r.m = m;
+    r.tau = tau;
+    r.norm = norm;
+    r.eps = eps;
+    r.eps_sq = eps * eps;
+    r.bits = NULL;
+    r.words = 0;
+    r.w = theiler;
+    oracle_rect_histograms(&r, na, nb, diag, vert, white, oracle_threads(threads));
+    return 0;
+}
+
+/* Histograms of a given n_rows x n_cols bit matrix (row-major 64-bit words,
+ * `words` per row, bit b of word c = column 64c+b); cells inside the Theiler
+ * band |i-j| < theiler count as 0.  Arrays hold max(n_rows, n_cols)+1 entries. */
+int rqa_oracle_matrix_histograms(const uint64_t *bits, int64_t n_rows, int64_t n_cols,
+                                 int64_t words, int theiler, uint64_t *diag, uint64_t *vert,
+                                 uint64_t *white, int threads)
+{
+    oracle_rect r;
+    if (!bits || !diag || !vert || !white || n_rows < 1 || n_cols < 1 || theiler < 0 ||
+        words < (n_cols + 63) / 64)
+        return -1;
+    memset(&r, 0, sizeof r);
+    r.bits = bits;
+    r.words = words;
+    r.w = theiler;
+    oracle_rect_histograms(&r, n_rows, n_cols, diag, vert, white, oracle_threads(threads));
+    return 0;
+}
+
 /* Measure vector layout (all FP64):
  *  0 RR  1 DET  2 L  3 Lmax  4 DIV  5 L_entr  6 LAM  7 TT  8 Vmax  9 V_entr
  * 10 W  11 Wmax 12 W_entr 13 N_rec 14 n */
 #define ORACLE_NMEAS 15
+
+/* Cells of an n_rows x n_cols matrix outside the band |i-j| < w, counted row by
+ * row. */
+static double oracle_rect_cells_outside_band(int64_t n_rows, int64_t n_cols, int64_t w)
+{
+    double band = 0.0;
+    int64_t i;
+    if (w <= 0)
+        return (double)n_rows * (double)n_cols;
+    for (i = 0; i < n_rows; ++i) {
+        int64_t lo = i - (w - 1), hi = i + (w - 1);
+        if (lo < 0)
+            lo = 0;
+        if (hi > n_cols - 1)
+            hi = n_cols - 1;
+        if (hi >= lo)
+            band += (double)(hi - lo + 1);
+    }
+    return (double)n_rows * (double)n_cols - band;
+}
 
 /* Cells outside the Theiler band: n^2 minus the band |i-j| < w. */
 static double oracle_cells_outside_band(int64_t n, int64_t w)
@@ -243,12 +456,13 @@ static double oracle_entropy(const uint64_t *h, int64_t n, int64_t from)
     return acc;
 }
 
-int rqa_oracle_measures(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
-                        int64_t n, int theiler, int lmin, int vmin, int wmin, double *out)
+/* Measures from histograms of `n` entries past index 0 over `cells` matrix
+ * cells outside the band; out[14] = n_report. */
+static void oracle_measures_core(const uint64_t *diag, const uint64_t *vert,
+                                 const uint64_t *white, int64_t n, double cells, int lmin,
+                                 int vmin, int wmin, double n_report, double *out)
 {
     double n_rec, det_num, lines_l, lam_num, v_all, lines_v, w_num, lines_w, lmax;
-    if (!diag || !vert || !white || !out || n < 1)
-        return -1;
     n_rec = oracle_sum(diag, n, 1, 1);
     det_num = oracle_sum(diag, n, lmin, 1);
     lines_l = oracle_sum(diag, n, lmin, 0);
@@ -259,7 +473,7 @@ int rqa_oracle_measures(const uint64_t *diag, const uint64_t *vert, const uint64
     lines_w = oracle_sum(white, n, wmin, 0);
     lmax = oracle_longest(diag, n);
 
-    out[0] = n_rec / oracle_cells_outside_band(n, theiler); /* RR */
+    out[0] = n_rec / cells;                                  /* RR */
     out[1] = det_num / n_rec;                                /* DET */
     out[2] = det_num / lines_l;                              /* L */
     out[3] = lmax;                                           /* Lmax */
@@ -273,8 +487,33 @@ int rqa_oracle_measures(const uint64_t *diag, const uint64_t *vert, const uint64
     out[11] = oracle_longest(white, n);                      /* Wmax */
     out[12] = oracle_entropy(white, n, wmin);                /* W_entr */
     out[13] = n_rec;
-    out[14] = (double)n;
+    out[14] = n_report;
     if (lmax == 0.0)
         out[4] = NAN;
+}
+
+int rqa_oracle_measures(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
+                        int64_t n, int theiler, int lmin, int vmin, int wmin, double *out)
+{
+    if (!diag || !vert || !white || !out || n < 1)
+        return -1;
+    oracle_measures_core(diag, vert, white, n, oracle_cells_outside_band(n, theiler), lmin,
+                         vmin, wmin, (double)n, out);
+    return 0;
+}
+
+/* Measures of an n_rows x n_cols matrix (cross recurrence or a given matrix):
+ * histograms of max(n_rows, n_cols)+1 entries; RR over the cells outside the
+ * band; out[14] = n_rows. */
+int rqa_oracle_rect_measures(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
+                             int64_t n_rows, int64_t n_cols, int theiler, int lmin, int vmin,
+                             int wmin, double *out)
+{
+    int64_t n = n_rows > n_cols ? n_rows : n_cols;
+    if (!diag || !vert || !white || !out || n_rows < 1 || n_cols < 1)
+        return -1;
+    oracle_measures_core(diag, vert, white, n,
+                         oracle_rect_cells_outside_band(n_rows, n_cols, theiler), lmin, vmin,
+                         wmin, (double)n_rows, out);
     return 0;
 }
