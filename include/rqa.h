@@ -49,7 +49,7 @@ extern "C" {
 #define RQA_EINVAL (-1)      /* an argument is out of range or a pointer is NULL   */
 #define RQA_ETOOSHORT (-2)   /* n_points gives fewer than one delay vector          */
 #define RQA_ENOMEM (-3)      /* device or host allocation failed                     */
-#define RQA_EDEVICE (-4)     /* a HIP runtime call or kernel launch failed           */
+#define RQA_EDEVICE (-4)     /* a HIP call, a launch or a device-side check failed  */
 #define RQA_ENONFINITE (-5)  /* the series holds NaN or +-Inf (detected on device)   */
 #define RQA_ESIZE (-6)       /* a caller buffer is shorter than required             */
 #define RQA_ESTATE (-7)      /* call order violated (e.g. result before run)         */
@@ -109,12 +109,46 @@ int rqa_hist_len(const rqa_handle *h, int64_t n_points, int64_t *len);
  * the device and reported by rqa_result. */
 int rqa_run(rqa_handle *h, const float *d_series, int64_t n_points, void *hip_stream);
 
-/* Wait for the last rqa_run, copy its histograms into caller-owned HOST arrays
- * of hist_len >= n+1 entries (any of diag/vert/white may be NULL) and fill *out
+/* Wait for the last rqa_run (or rqa_run_cross / rqa_run_matrix), copy its
+ * histograms into caller-owned HOST arrays of hist_len >= n+1 entries
+ * (max(rows, columns)+1 for the full-matrix runs; any of diag/vert/white may
+ * be NULL) and fill *out
  * (may be NULL).  RQA_ESTATE without a prior run, RQA_ESIZE if hist_len is too
  * small, RQA_ENONFINITE if the series held NaN/Inf. */
 int rqa_result(rqa_handle *h, rqa_measures *out, uint64_t *diag, uint64_t *vert,
                uint64_t *white, int64_t hist_len);
+
+/* Cross recurrence quantification (cRQA, Sect. 3.3: the delay vectors of two
+ * series on the two axes; Sect. 4.2: a non-symmetric matrix has 2N-1 diagonals).
+ * Rows are the vectors of series a, columns those of series b, both embedded
+ * with h's m and tau and compared with h's norm and radius; the Theiler window
+ * masks cells with |i-j| < theiler by index (0 for none).  Every diagonal
+ * k = j - i in [-(n_a-1), n_b-1] and every column (over all n_a rows) is walked
+ * once; runs are counted once.  d_a / d_b: na_points / nb_points contiguous FP32
+ * values in device memory, owned by the caller and kept alive until
+ * rqa_result returns.  Asynchronous on hip_stream like rqa_run; fetch with
+ * rqa_result, whose histograms then have max(n_a, n_b)+1 entries (see
+ * rqa_cross_hist_len) and whose RR is over the n_a*n_b cells outside the band;
+ * rqa_measures.n_vec reports n_a.  RQA_ETOOSHORT if either series has fewer
+ * points than (m-1)*tau+1. */
+int rqa_run_cross(rqa_handle *h, const float *d_a, int64_t na_points, const float *d_b,
+                  int64_t nb_points, void *hip_stream);
+
+/* Histogram length max(n_a, n_b)+1 of rqa_run_cross for these series lengths. */
+int rqa_cross_hist_len(const rqa_handle *h, int64_t na_points, int64_t nb_points,
+                       int64_t *len);
+
+/* Quantification of a precomputed recurrence matrix (Sect. 9 lists it among
+ * the planned features): the same three histograms and measures for a given
+ * n_rows x n_cols binary matrix in device memory, row-major, words_per_row
+ * (>= ceil(n_cols/64)) 64-bit words per row, bit b of word c of row i = cell
+ * (i, 64c+b); bits past column n_cols-1 are ignored.  The matrix is not assumed
+ * symmetric: every diagonal and column is walked once.  Only h's minimum line
+ * lengths and Theiler window (cells |i-j| < theiler count as 0) are used.  The
+ * caller owns d_bits and keeps it alive until rqa_result returns; histograms
+ * have max(n_rows, n_cols)+1 entries.  Asynchronous like rqa_run. */
+int rqa_run_matrix(rqa_handle *h, const uint64_t *d_bits, int64_t n_rows, int64_t n_cols,
+                   int64_t words_per_row, void *hip_stream);
 
 /* Batched windowed RQA (many windows of uneven length over one device series,
  * one persistent launch; the RQA X "epochs" idea of Sect. 3 run in parallel).

@@ -155,7 +155,9 @@ struct rqa_handle {
     bool has_run = false;
     bool batched = false;
     hipStream_t stream = nullptr;
-    std::vector<int64_t> nvec;      // per job
+    std::vector<int64_t> nvec;      // per job: rows (delay vectors)
+    std::vector<int64_t> ncols;     // per job: columns
+    std::vector<int64_t> hlen;      // per job: histogram entries
     std::vector<size_t> job_off;    // per job: byte offset of its histograms in ws.base
     size_t info_block_off = 0;      // info records (flag + statistics) of all jobs
     size_t hist_block_off = 0;      // histograms of all jobs, contiguous
@@ -236,57 +238,27 @@ int capture_graph(rqa_handle *h, const std::vector<Job> &jobs, char *base, uint6
     return RQA_OK;
 }
 
-int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_t *offsets,
-            const int64_t *lengths, int32_t count, void *stream, bool batched) {
-    if (!h || !d_series) return RQA_EINVAL;
-    std::vector<Job> jobs(count);
-    const KParams kp = make_kparams(h->p);
-    std::vector<int64_t> nvec(count);
+// Lay out the workspace for `jobs` and enqueue them: [launch scratch][info
+// records of every job][histograms of every job][job scratch], so that a fetch
+// copies the small records in one go and the histograms, when asked for, in one
+// more.  `sig` identifies the launch apart from the workspace; an identical
+// repeat replays a captured graph.
+int launch(rqa_handle *h, std::vector<Job> &jobs, int waves, bool trial, const std::string &key,
+           uint64_t sig, void *stream, bool batched) {
+    const int32_t count = static_cast<int32_t>(jobs.size());
+    std::vector<int64_t> nvec(count), ncols(count), hlen(count);
     std::vector<size_t> off(count);
-    int64_t nmax = 0;
-    for (int32_t w = 0; w < count; ++w) {
-        const int64_t o = offsets ? offsets[w] : 0;
-        const int64_t len = lengths ? lengths[w] : n_points;
-        if (o < 0 || len < 0 || o > n_points || len > n_points - o) return RQA_EINVAL;
-        const int64_t nv = len - static_cast<int64_t>(h->p.m - 1) * h->p.tau;
-        if (nv < 1) return RQA_ETOOSHORT;
-        if (nv > (int64_t(1) << 31) - 2) return RQA_EINVAL;
-        Job &jb = jobs[w];
-        jb.series = d_series + o;
-        jb.n_points = len;
-        jb.n_vec = nv;
-        jb.kp = kp;
-        nvec[w] = nv;
-        nmax = std::max(nmax, nv);
-    }
-
-    // Workgroup shape: fixed by rqa_set_tiling, else tuned per signature.
-    bool trial = false;
-    int waves = h->waves;
-    std::string key;
-    if (waves == 0) {
-        key = tune_key(h->p, nmax, count);
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        TuneEntry &e = g_tune[key];
-        if (e.done) {
-            waves = e.best;
-        } else {
-            waves = kCandidates[e.next];
-            trial = true;
-        }
-    }
-    // Workspace: [launch scratch][info records of every job][histograms of every
-    // job][job scratch], so that a fetch copies the small records in one go and
-    // the histograms, when asked for, in one more.
     size_t total = align256(engine_launch_scratch_bytes(count));
     const size_t info_block_off = total;
     total += align256(kInfoBytes * static_cast<size_t>(count));
     const size_t hist_block_off = total;
     for (int32_t w = 0; w < count; ++w) {
         jobs[w].waves = waves;
+        nvec[w] = jobs[w].n_vec;
+        ncols[w] = jobs[w].mode == kModeAuto ? jobs[w].n_vec : jobs[w].n_cols;
+        hlen[w] = jobs[w].hist_len();
         off[w] = total;
-        total += align256(sizeof(uint64_t) * 3 * static_cast<size_t>(jobs[w].n_vec + 1));
+        total += align256(sizeof(uint64_t) * 3 * static_cast<size_t>(hlen[w]));
     }
     const size_t hist_block_bytes = total - hist_block_off;
     std::vector<size_t> soff(count);
@@ -322,13 +294,6 @@ int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
 
-    // Signature of this launch: identical repeats replay a captured graph.
-    uint64_t sig = 1469598103934665603ull;
-    sig = fnv(sig, &d_series, sizeof d_series);
-    sig = fnv(sig, &n_points, sizeof n_points);
-    sig = fnv(sig, &count, sizeof count);
-    if (offsets) sig = fnv(sig, offsets, sizeof(int64_t) * count);
-    if (lengths) sig = fnv(sig, lengths, sizeof(int64_t) * count);
     sig = fnv(sig, &h->p, sizeof h->p);
     sig = fnv(sig, &waves, sizeof waves);
     sig = fnv(sig, &h->groups, sizeof h->groups);
@@ -357,6 +322,8 @@ int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_
     h->trial_waves = waves;
     h->trial_key = key;
     h->nvec = std::move(nvec);
+    h->ncols = std::move(ncols);
+    h->hlen = std::move(hlen);
     h->job_off = std::move(off);
     h->info_block_off = info_block_off;
     h->hist_block_off = hist_block_off;
@@ -367,6 +334,76 @@ int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_
     h->has_run = true;
     h->batched = batched;
     return RQA_OK;
+}
+
+int enqueue(rqa_handle *h, const float *d_series, int64_t n_points, const int64_t *offsets,
+            const int64_t *lengths, int32_t count, void *stream, bool batched) {
+    if (!h || !d_series) return RQA_EINVAL;
+    std::vector<Job> jobs(count);
+    const KParams kp = make_kparams(h->p);
+    int64_t nmax = 0;
+    for (int32_t w = 0; w < count; ++w) {
+        const int64_t o = offsets ? offsets[w] : 0;
+        const int64_t len = lengths ? lengths[w] : n_points;
+        if (o < 0 || len < 0 || o > n_points || len > n_points - o) return RQA_EINVAL;
+        const int64_t nv = len - static_cast<int64_t>(h->p.m - 1) * h->p.tau;
+        if (nv < 1) return RQA_ETOOSHORT;
+        if (nv > (int64_t(1) << 31) - 2) return RQA_EINVAL;
+        Job &jb = jobs[w];
+        jb.series = d_series + o;
+        jb.n_points = len;
+        jb.n_vec = nv;
+        jb.n_cols = nv;
+        jb.kp = kp;
+        nmax = std::max(nmax, nv);
+    }
+
+    // Workgroup shape: fixed by rqa_set_tiling, else tuned per signature.
+    bool trial = false;
+    int waves = h->waves;
+    std::string key;
+    if (waves == 0) {
+        key = tune_key(h->p, nmax, count);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        TuneEntry &e = g_tune[key];
+        if (e.done) {
+            waves = e.best;
+        } else {
+            waves = kCandidates[e.next];
+            trial = true;
+        }
+    }
+    uint64_t sig = 1469598103934665603ull;
+    const int32_t mode = kModeAuto;
+    sig = fnv(sig, &mode, sizeof mode);
+    sig = fnv(sig, &d_series, sizeof d_series);
+    sig = fnv(sig, &n_points, sizeof n_points);
+    sig = fnv(sig, &count, sizeof count);
+    if (offsets) sig = fnv(sig, offsets, sizeof(int64_t) * count);
+    if (lengths) sig = fnv(sig, lengths, sizeof(int64_t) * count);
+    return launch(h, jobs, waves, trial, key, sig, stream, batched);
+}
+
+// One job over a full (not symmetric) matrix: the cross recurrence matrix of
+// (a, b), or a given bit matrix.
+int enqueue_full(rqa_handle *h, Job jb, void *stream) {
+    if (jb.n_vec > (int64_t(1) << 31) - 2 || jb.n_cols > (int64_t(1) << 31) - 2)
+        return RQA_EINVAL;
+    jb.kp = make_kparams(h->p);
+    const int waves = h->waves > 0 ? h->waves : engine_default_waves(jb.n_vec);
+    std::vector<Job> jobs(1, jb);
+    uint64_t sig = 1469598103934665603ull;
+    sig = fnv(sig, &jb.mode, sizeof jb.mode);
+    sig = fnv(sig, &jb.series, sizeof jb.series);
+    sig = fnv(sig, &jb.n_points, sizeof jb.n_points);
+    sig = fnv(sig, &jb.series_b, sizeof jb.series_b);
+    sig = fnv(sig, &jb.n_points_b, sizeof jb.n_points_b);
+    sig = fnv(sig, &jb.bits, sizeof jb.bits);
+    sig = fnv(sig, &jb.n_vec, sizeof jb.n_vec);
+    sig = fnv(sig, &jb.n_cols, sizeof jb.n_cols);
+    sig = fnv(sig, &jb.words, sizeof jb.words);
+    return launch(h, jobs, waves, false, std::string(), sig, stream, false);
 }
 
 // Record the tile-phase time of a finished autotuning trial.
@@ -397,7 +434,8 @@ int fetch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag, uint6
     if (!h->has_run) return RQA_ESTATE;
     if (index < 0 || index >= static_cast<int32_t>(h->nvec.size())) return RQA_EINVAL;
     const int64_t n = h->nvec[index];
-    if ((diag || vert || white) && hist_len < n + 1) return RQA_ESIZE;
+    const int64_t hl = h->hlen[index];
+    if ((diag || vert || white) && hist_len < hl) return RQA_ESIZE;
     // Grow a pinned host buffer.
     auto grow = [](void **buf, size_t *have, size_t need) -> int {
         if (*have >= need) return RQA_OK;
@@ -442,15 +480,15 @@ int fetch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag, uint6
         }
         const uint64_t *hd = reinterpret_cast<const uint64_t *>(
             reinterpret_cast<const char *>(h->host_cache) + (h->job_off[index] - h->hist_block_off));
-        const uint64_t *hv = hd + (n + 1), *hw = hv + (n + 1);
-        if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * (n + 1));
-        if (vert) std::memcpy(vert, hv, sizeof(uint64_t) * (n + 1));
-        if (white) std::memcpy(white, hw, sizeof(uint64_t) * (n + 1));
+        const uint64_t *hv = hd + hl, *hw = hv + hl;
+        if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * hl);
+        if (vert) std::memcpy(vert, hv, sizeof(uint64_t) * hl);
+        if (white) std::memcpy(white, hw, sizeof(uint64_t) * hl);
     }
     if (out) {
         JobStats st;
         std::memcpy(&st, info + 8, sizeof st);
-        measures_from_stats(st, n, h->p, out);
+        measures_from_stats(st, n, h->ncols[index], h->p, out);
     }
     return RQA_OK;
 }
@@ -484,6 +522,44 @@ int rqa_run(rqa_handle *h, const float *d_series, int64_t n_points, void *hip_st
     if (!h) return RQA_EINVAL;
     if (n_points < 0) return RQA_EINVAL;
     return enqueue(h, d_series, n_points, nullptr, nullptr, 1, hip_stream, false);
+}
+
+int rqa_cross_hist_len(const rqa_handle *h, int64_t na_points, int64_t nb_points, int64_t *len) {
+    if (!h || !len) return RQA_EINVAL;
+    const int64_t d = static_cast<int64_t>(h->p.m - 1) * h->p.tau;
+    const int64_t na = na_points - d, nb = nb_points - d;
+    if (na < 1 || nb < 1) return RQA_ETOOSHORT;
+    *len = std::max(na, nb) + 1;
+    return RQA_OK;
+}
+
+int rqa_run_cross(rqa_handle *h, const float *d_a, int64_t na_points, const float *d_b,
+                  int64_t nb_points, void *hip_stream) {
+    if (!h || !d_a || !d_b || na_points < 0 || nb_points < 0) return RQA_EINVAL;
+    const int64_t d = static_cast<int64_t>(h->p.m - 1) * h->p.tau;
+    Job jb;
+    jb.mode = kModeCross;
+    jb.series = d_a;
+    jb.n_points = na_points;
+    jb.n_vec = na_points - d;
+    jb.series_b = d_b;
+    jb.n_points_b = nb_points;
+    jb.n_cols = nb_points - d;
+    if (jb.n_vec < 1 || jb.n_cols < 1) return RQA_ETOOSHORT;
+    return enqueue_full(h, jb, hip_stream);
+}
+
+int rqa_run_matrix(rqa_handle *h, const uint64_t *d_bits, int64_t n_rows, int64_t n_cols,
+                   int64_t words_per_row, void *hip_stream) {
+    if (!h || !d_bits || n_rows < 1 || n_cols < 1 || words_per_row < (n_cols + 63) / 64)
+        return RQA_EINVAL;
+    Job jb;
+    jb.mode = kModeMatrix;
+    jb.n_vec = n_rows;
+    jb.n_cols = n_cols;
+    jb.bits = d_bits;
+    jb.words = words_per_row;
+    return enqueue_full(h, jb, hip_stream);
 }
 
 int rqa_result(rqa_handle *h, rqa_measures *out, uint64_t *diag, uint64_t *vert, uint64_t *white,

@@ -40,16 +40,34 @@ static_assert(8 + sizeof(JobStats) <= kInfoBytes, "info record too small");
 
 KParams make_kparams(const rqa_params &p);
 
-// One independent RQA problem inside a launch: a window of a device series.
+// What a job's matrix is.
+enum JobMode : int32_t {
+    kModeAuto = 0,     // recurrence matrix of one series (symmetric; upper triangle evaluated)
+    kModeCross = 1,    // cross recurrence matrix: rows from series a, columns from series b
+    kModeMatrix = 2,   // a given bit matrix (row-major 64-bit words)
+};
+
+// One independent RQA problem inside a launch: a window of a device series, a
+// pair of series (cross recurrence) or a given bit matrix.
 struct Job {
-    const float *series = nullptr;  // first point of the window (device)
+    int32_t mode = kModeAuto;
+    const float *series = nullptr;  // first point of the window (device); rows' series
     int64_t n_points = 0;           // points in the window
-    int64_t n_vec = 0;              // delay vectors
-    uint64_t *hist = nullptr;       // device: 3*(n_vec+1) u64 -- diag | vert | white
+    int64_t n_vec = 0;              // delay vectors (rows)
+    const float *series_b = nullptr;   // cross: columns' series (device)
+    int64_t n_points_b = 0;
+    int64_t n_cols = 0;             // columns (auto: n_vec)
+    const uint64_t *bits = nullptr; // given matrix (device): n_vec rows of `words` u64
+    int64_t words = 0;
+    uint64_t *hist = nullptr;       // device: 3*hist_len() u64 -- diag | vert | white
     int *flag = nullptr;            // device info record (kInfoBytes): flag at 0, JobStats at 8
     void *scratch = nullptr;        // device: engine_job_scratch_bytes(*this) bytes
     KParams kp{};                   // parameters of this job
     int waves = 0;                  // waves per workgroup (strip height 64*waves), > 0
+    // Histogram entries (index = line length, 0 unused): longest line + 1.
+    int64_t hist_len() const {
+        return (mode == kModeAuto ? n_vec : (n_cols > n_vec ? n_cols : n_vec)) + 1;
+    }
 };
 
 // Device workspace owned by a handle (or a served job); grown on demand.
@@ -105,8 +123,10 @@ int engine_launch(const std::vector<Job> &jobs, void *launch_scratch, void *stag
 void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
                         int64_t n, const rqa_params &p, rqa_measures *out);
 
-// Host FP64 measures from the device-reduced statistics.
-void measures_from_stats(const JobStats &st, int64_t n, const rqa_params &p, rqa_measures *out);
+// Host FP64 measures from the device-reduced statistics of an n_rows x n_cols
+// matrix (n_cols = n_rows for the recurrence matrix of one series).
+void measures_from_stats(const JobStats &st, int64_t n_rows, int64_t n_cols, const rqa_params &p,
+                         rqa_measures *out);
 
 int validate_params(const rqa_params &p);
 

@@ -4,6 +4,7 @@
 // LAM, TT, Vmax, V_entr) plus the white-vertical analogues (W, Wmax, W_entr),
 // derived from the frequency distributions of the three line types (Sect. 2).
 // Sums run over ascending line length; empty denominators give NaN.
+#include <algorithm>
 #include <cmath>
 #include <limits>
 
@@ -44,6 +45,21 @@ double cells_outside_band(int64_t n, int64_t w) {
                         2.0 * (static_cast<double>(kmax) * static_cast<double>(n) -
                                0.5 * static_cast<double>(kmax) * static_cast<double>(kmax + 1));
     return nn - band;
+}
+
+// Cells of an n_rows x n_cols matrix outside the band |i-j| < w: every cell
+// minus the lengths of the band diagonals k = -(w-1) .. w-1.
+double cells_outside_band_rect(int64_t n_rows, int64_t n_cols, int64_t w) {
+    const double all = static_cast<double>(n_rows) * static_cast<double>(n_cols);
+    if (w <= 0) return all;
+    double band = 0.0;
+    const int64_t klo = -std::min(w - 1, n_rows - 1), khi = std::min(w - 1, n_cols - 1);
+    for (int64_t k = klo; k <= khi; ++k) {
+        // diagonal k = j - i: rows max(0,-k) .. min(n_rows, n_cols - k) - 1
+        const int64_t len = std::min(n_rows, n_cols - k) - std::max<int64_t>(0, -k);
+        if (len > 0) band += static_cast<double>(len);
+    }
+    return all - band;
 }
 
 // Count, mass (sum of lengths), longest line and the count/mass over lengths
@@ -98,12 +114,15 @@ void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64
     out->w_entr = entropy(white, n, p.wmin, w.min.count);
 }
 
-void measures_from_stats(const JobStats &st, int64_t n, const rqa_params &p, rqa_measures *out) {
+void measures_from_stats(const JobStats &st, int64_t n_rows, int64_t n_cols, const rqa_params &p,
+                         rqa_measures *out) {
     const double nan = std::numeric_limits<double>::quiet_NaN();
     auto dbl = [](uint64_t v) { return static_cast<double>(v); };
-    out->n_vec = n;
+    out->n_vec = n_rows;
     out->n_rec = st.mass_all[0];
-    out->rr = ratio(dbl(st.mass_all[0]), cells_outside_band(n, p.theiler));
+    const double cells = n_rows == n_cols ? cells_outside_band(n_rows, p.theiler)
+                                          : cells_outside_band_rect(n_rows, n_cols, p.theiler);
+    out->rr = ratio(dbl(st.mass_all[0]), cells);
     out->det = ratio(dbl(st.mass_min[0]), dbl(st.mass_all[0]));
     out->l = ratio(dbl(st.mass_min[0]), dbl(st.cnt_min[0]));
     out->lmax = dbl(st.longest[0]);

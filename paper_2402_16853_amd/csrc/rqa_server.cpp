@@ -284,7 +284,7 @@ int collect(rqa_server *srv, ServedJob *j, rqa_measures *out, uint64_t *diag, ui
         if (out) {
             JobStats stats;
             std::memcpy(&stats, reinterpret_cast<const char *>(hw + (n + 1)) + 8, sizeof stats);
-            measures_from_stats(stats, n, j->p, out);
+            measures_from_stats(stats, n, n, j->p, out);
         }
     }
     srv->jobs.erase(j->ticket);

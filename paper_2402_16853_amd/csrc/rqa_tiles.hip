@@ -17,9 +17,10 @@
 // Geometry.  n delay vectors, w' = max(theiler, 1).  U = {(i,j): j - i >= w'}.
 // A workgroup of W waves owns a strip of H = 64*W consecutive rows; wave w owns
 // rows R = R0 + 64w .. R+63, one row per lane, and walks the 64-column tiles
-// c = c0 .. c_last of its strip left to right.  The waves run as a pipeline with
-// one tile of lag per wave (one barrier per step), so wave w consumes at step t
-// what wave w-1 produced for the same tile at step t-1.
+// c = c0 .. c_last of its strip left to right.  The waves run as a pipeline:
+// wave w consumes the carries that wave w-1 produced for the same tile, through
+// an LDS ring per wave pair with produced / consumed counters (no workgroup
+// barrier per tile; a wave may run up to kRing tiles ahead of the one below).
 //
 // Full-matrix lines from U:
 //  * a diagonal k >= w' of U and its mirror -k: each run counted twice;
@@ -61,13 +62,19 @@ constexpr int kCapD = 1024;    // LDS bins for diagonal lengths < kCapD
 constexpr int kCapV = 1024;    // LDS bins for vertical lengths < kCapV
 constexpr int kCapW = 6016;    // LDS bins for white-vertical lengths < kCapW
 constexpr int kMaxM = 6;       // embedding dimensions held in registers
+constexpr int kRing = 4;       // carry slots per pair of consecutive waves (tiles in flight)
+constexpr uint32_t kSpinLimit = 1u << 20;   // polls (~28 ms) before a neighbour wait gives up
 constexpr int kStitchThreads = 256;
 constexpr int kStatThreads = 256;
 constexpr int kStatMaxBlocks = 64;
 
 // Device-side description of one job (one series or window).
 struct JobDesc {
-    const float *s;            // series (n_points values)
+    const float *s;            // series of the rows (n_points values)
+    const float *sb;           // series of the columns (auto: s)
+    const uint64_t *bits;      // given matrix: n rows of `words` u64 (bit b of word c = column 64c+b)
+    int64_t words;
+    int64_t n_points_b;        // points of sb
     const float *tail;         // coordinates of the last column tile, zero padded
     unsigned long long *hd;    // histograms, n+1 entries each
     unsigned long long *hv;
@@ -79,12 +86,15 @@ struct JobDesc {
     uint16_t *dfirst;          // per (strip, diagonal): black run at the top edge
     uint16_t *dlast;           // per (strip, diagonal): black run at the bottom edge
     int64_t n_points;
-    int32_t n;                 // delay vectors
+    int32_t n;                 // delay vectors (rows)
+    int32_t nb;                // columns (auto: n)
+    int32_t hmax;              // longest possible line; histograms hold hmax+1 entries
+    int32_t mode;              // JobMode
     int32_t m, tau, norm, theiler, wp;
     float thr;                 // eps (L1, Linf) or fl32(eps*eps) (L2)
     int32_t H;                 // strip height
     int32_t nstrips;
-    int32_t c_last;            // last column tile (n-1)/64
+    int32_t c_last;            // last column tile (nb-1)/64
     int32_t tail_len;          // floats in tail
     int32_t strip_base;        // first work item of this job within its group
     int32_t stitch_block0;     // first stitch block of this job
@@ -217,37 +227,39 @@ struct LineCtx {
     uint32_t row;       // row index (horizontal)
 };
 
-// A run of colour `c` and length `len` has ended.
-template <int KIND>
+// A run of colour `c` and length `len` has ended.  DW: how many lines a
+// diagonal run stands for (2 in the upper triangle of a symmetric matrix, whose
+// mirror diagonal repeats it; 1 in a full matrix).
+template <int KIND, int DW = 2>
 __device__ __forceinline__ void finish_run(const LineCtx &lc, uint32_t c, uint32_t len, uint32_t first) {
     const JobDesc &j = *lc.jd;
     if (KIND == kDiag) {
         if (first) {
             if (lc.sum_ok) j.dfirst[lc.sum_idx] = (uint16_t)(c ? len : 0u);
         } else if (c) {
-            emit(lc.bins.d, kCapD, j.hd, len, 2u, (uint32_t)j.n, j.flag);
+            emit(lc.bins.d, kCapD, j.hd, len, (uint32_t)DW, (uint32_t)j.hmax, j.flag);
         }
     } else if (KIND == kVert) {
         if (first)
             j.vfirst[lc.sum_idx] = (uint16_t)(len | (c << 15));
         else if (c)
-            emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.n, j.flag);
+            emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
         else
-            emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.n, j.flag);
+            emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
     } else {
         if (first)
             j.lead[lc.row] = len | (c << 31);
         else if (c)
-            emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.n, j.flag);
+            emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
         else
-            emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.n, j.flag);
+            emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
     }
 }
 
 // Advance `st` over the bits [lo, hi) of x (win = mask of those bits),
 // finishing every run that ends there.  The common case -- no colour change in
 // the window -- costs a few VALU operations.
-template <int KIND>
+template <int KIND, int DW = 2>
 __device__ __forceinline__ void run_segment(uint64_t x, uint64_t win, uint32_t lo, uint32_t hi,
                                             Run &st, const LineCtx &lc) {
     uint64_t diff = (st.color ? ~x : x) & win;
@@ -258,7 +270,7 @@ __device__ __forceinline__ void run_segment(uint64_t x, uint64_t win, uint32_t l
     uint32_t pos = lo;
     while (true) {
         const uint32_t p = (uint32_t)__builtin_ctzll(diff);
-        finish_run<KIND>(lc, st.color, st.len + (p - pos), st.first);
+        finish_run<KIND, DW>(lc, st.color, st.len + (p - pos), st.first);
         st.first = 0;
         st.color ^= 1u;
         st.len = 0;
@@ -368,7 +380,7 @@ __global__ void k_prepare(const JobDesc *__restrict__ jobs) {
     const JobDesc &j = jobs[blockIdx.y];
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t hl = (int64_t)j.n + 1;
+    const int64_t hl = (int64_t)j.hmax + 1;
     for (int64_t t = tid; t < hl; t += stride) {
         j.hd[t] = 0ull;
         j.hv[t] = 0ull;
@@ -376,13 +388,17 @@ __global__ void k_prepare(const JobDesc *__restrict__ jobs) {
     }
     if (tid < (int64_t)(sizeof(JobStats) / 8))
         reinterpret_cast<unsigned long long *>(j.stats)[tid] = 0ull;
+    if (j.mode == kModeMatrix) return;   // a given matrix has no series
     bool bad = false;
     for (int64_t t = tid; t < j.n_points; t += stride) bad |= !__builtin_isfinite(j.s[t]);
+    if (j.mode == kModeCross)
+        for (int64_t t = tid; t < j.n_points_b; t += stride) bad |= !__builtin_isfinite(j.sb[t]);
     if (bad) atomicOr(j.flag, 1);   // bit 0: non-finite input
+    // Column coordinates of the last tile, from the columns' series.
     const int64_t base = (int64_t)j.c_last * 64;
     float *tail = const_cast<float *>(j.tail);
     for (int64_t t = tid; t < j.tail_len; t += stride)
-        tail[t] = base + t < j.n_points ? j.s[base + t] : 0.0f;
+        tail[t] = base + t < j.n_points_b ? j.sb[base + t] : 0.0f;
 }
 
 // Reset the non-finite flags and the work counters (runs before k_prepare).
@@ -396,16 +412,18 @@ __global__ void k_reset(const JobDesc *__restrict__ jobs, int njobs, int *counte
 // Kernel 2: the fused tile pass.  Persistent workgroups pull (job, strip) work
 // items of one (norm, m) group from a counter.
 // ---------------------------------------------------------------------------
-// LDS of a tile workgroup (dynamic shared memory): privatised histogram bins,
-// the double-buffered carry slots between consecutive waves (vertical and
-// diagonal states, one u32 per lane), and the current work item.  Sized for
-// the launch's wave count (40 KB for 8 waves).  The kernel is compiled for six
-// waves per SIMD (at most 80 VGPRs, no spills), i.e. three 8-wave workgroups
-// per CU; the LDS would allow four.
+// LDS of a tile workgroup (dynamic shared memory): privatised histogram bins;
+// for each pair of consecutive waves a ring of kRing carry slots (vertical and
+// diagonal states of one tile, one u32 per lane); the produced / consumed tile
+// counters of those rings; the current work item.  Sized for the launch's wave
+// count (48 KB for 8 waves).  The kernel is compiled for six waves per SIMD (at
+// most 80 VGPRs, no spills), i.e. three 8-wave workgroups per CU.
 struct StripLds {
     uint32_t *bd, *bv, *bw;
-    uint32_t *vslot;    // [2][waves][64]
-    uint32_t *dslot;    // [2][waves][64]
+    uint32_t *vslot;    // [kRing][waves][64]
+    uint32_t *dslot;    // [kRing][waves][64]
+    int *prod;          // [kMaxWaves]: tiles whose carries wave w has written
+    int *cons;          // [kMaxWaves]: tiles whose carries wave w+1 has read
     int *item;
     int nw;
     __device__ uint32_t &vs(int buf, int w, int lane) { return vslot[(buf * nw + w) * 64 + lane]; }
@@ -413,11 +431,28 @@ struct StripLds {
 };
 
 __host__ __device__ constexpr size_t strip_lds_bytes(int waves) {
-    return sizeof(uint32_t) * ((size_t)kCapD + kCapV + kCapW + 2 * 2 * (size_t)waves * 64) + 16;
+    return sizeof(uint32_t) * ((size_t)kCapD + kCapV + kCapW + 2 * (size_t)kRing * waves * 64 +
+                               2 * kMaxWaves) + 16;
+}
+
+// Wait (wave-uniform) until the counter reaches `target`.  Each wait is bounded:
+// past kSpinLimit polls it gives up and returns false, so a wave never hangs.
+__device__ __forceinline__ bool wait_counter(int *ctr, int target) {
+    for (uint32_t spin = 0;; ++spin) {
+        const int v = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (v >= target) return true;
+        if (spin >= kSpinLimit) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__device__ __forceinline__ void publish_counter(int *ctr, int value) {
+    __hip_atomic_store(ctr, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ void flush_bins(const StripLds &L, const JobDesc &j) {
-    const int hl = j.n + 1;
+    const int hl = j.hmax + 1;
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
         if (t < kCapD) {
             const uint32_t v = L.bd[t];
@@ -432,59 +467,113 @@ __device__ void flush_bins(const StripLds &L, const JobDesc &j) {
     }
 }
 
-template <int NORM, int M>
+// One strip of one job.  MODE kModeAuto: the upper triangle U of the symmetric
+// recurrence matrix of one series (horizontal runs are the row segments of the
+// full columns, joined through the band by the stitch).  MODE kModeCross /
+// kModeMatrix: a full n x nb matrix that is not symmetric (every diagonal and
+// every column walked once; no horizontal runs).
+template <int NORM, int M, int MODE>
 __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
     static_assert(kMaxWaves <= 8, "LDS budget assumes at most 8 waves per workgroup");
+    constexpr bool FULL = MODE != kModeAuto;
+    constexpr int kDW = FULL ? 1 : 2;   // lines per diagonal run found
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int nw = blockDim.x >> 6;
-    const int n = j.n, wp = j.wp, H = j.H, tau = j.tau;
+    const int n = j.n, wp = j.wp, H = j.H, tau = j.tau;   // n: rows
+    const int nb = FULL ? j.nb : n;                        // columns
+    const int64_t band = j.theiler;                        // full matrix: cells |i-j| < band are 0
     const int R0 = strip * H;
     const int R = R0 + 64 * wave;
     const int i = R + lane;                      // this lane's row
-    const int c0 = (R0 + wp) >> 6;
+    const int c0 = FULL ? 0 : (R0 + wp) >> 6;
     const int T = j.c_last - c0 + 1;             // tiles of the strip
-    const bool wave_has_u = R + wp <= n - 1;     // some row of this wave has U cells
-    const int cfirst = (R + wp) >> 6;            // first tile with U cells for this wave
-    const int64_t soff = strip_offset(strip, n, wp, H);
+    // Some row of this wave has cells to walk, and the first tile that has.
+    const bool wave_has_u = FULL ? R <= n - 1 : R + wp <= n - 1;
+    const int cfirst = FULL ? 0 : (R + wp) >> 6;
+    const int64_t soff = FULL ? 0 : strip_offset(strip, n, wp, H);
+    // Summary slots: auto -- per (strip, column / diagonal of U) in triangular
+    // strip order; full -- per strip nb columns and nb+H-1 diagonals
+    // k = -(R0+H-1) .. nb-1-R0.
+    const int64_t vbase = FULL ? (int64_t)strip * nb : soff - R0 - wp;
+    const int64_t dbase = FULL ? (int64_t)strip * (nb + H - 1) + (R0 + H - 1) : soff - wp;
+    auto dok = [&](int k) -> bool {
+        return FULL ? (k >= -(R0 + H - 1) && k <= nb - 1 - R0) : (k >= wp && k <= n - 1 - R0);
+    };
 
     // Row coordinates of this lane (clamped for rows past the end).
     const int irow = i < n ? i : n - 1;
-    const float *rowp = j.s + irow;
-    float xr[M > 0 ? M : 1];
+    const float *rowp = MODE == kModeMatrix ? nullptr : j.s + irow;
+    float xr[M > 0 ? M : 1] = {};
+    if constexpr (MODE != kModeMatrix) {
 #pragma unroll
-    for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? rowp[(int64_t)k * tau] : 0.0f;
+        for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? rowp[(int64_t)k * tau] : 0.0f;
+    }
 
     Bins bins{L.bd, L.bv, L.bw};
     const LineCtx hctx{&j, bins, 0, false, (uint32_t)i};
-    Run hs{0, 0, 0};          // horizontal run of this lane's row
+    Run hs{0, 0, 0};          // horizontal run of this lane's row (auto)
     bool hstarted = false;
     Run left{0, 0, 0};        // diagonal carry from the previous tile (upper part end)
 
-    const int nsteps = T + nw - 1;
-    for (int step = 0; step < nsteps; ++step) {
-        const int t = step - wave;
+    // The waves form a pipeline over the tiles: wave w reads the carries that
+    // wave w-1 wrote for the same tile and writes its own for wave w+1, through a
+    // ring of kRing slots per wave pair.  A wave waits only for its neighbours:
+    // for the tile's carries from above and for a free slot below.
+    const int tfirst = cfirst - c0;              // first tile with cells for this wave
+    if (wave > 0) publish_counter(&L.cons[wave - 1], wave_has_u ? tfirst : 0x7FFFFFFF);
+    bool sync_ok = true;
+    for (int t = wave_has_u ? tfirst : T; t < T; ++t) {
         const int c = c0 + t;
-        if (wave_has_u && t >= 0 && t < T && c >= cfirst) {
+        const int slot = t & (kRing - 1);
+        {
             const int jbase = c * 64;
-            const ConstF cols = to_const((c == j.c_last) ? j.tail : j.s + jbase);
             uint32_t xlo, xhi;
-            tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, xlo, xhi);
+            if constexpr (MODE == kModeMatrix) {
+                const uint64_t word = i < n ? j.bits[(int64_t)i * j.words + c] : 0ull;
+                xlo = (uint32_t)word;
+                xhi = (uint32_t)(word >> 32);
+            } else {
+                const ConstF cols = to_const((c == j.c_last) ? j.tail : j.sb + jbase);
+                tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, xlo, xhi);
+            }
 
-            // Interior tile: every row has started before this tile and every
-            // column continues below this wave, so no cell needs masking.
-            const bool interior = jbase >= R + 64 + wp && jbase + 63 <= n - 1;
+            // Interior tile: no cell needs masking, and every column and
+            // diagonal continues below this wave.
+            bool interior;
+            if constexpr (FULL) {
+                interior = R + 64 <= n - 1 && jbase + 63 <= nb - 1 &&
+                           (band == 0 || (int64_t)jbase - (R + 63) >= band ||
+                            (int64_t)R - (jbase + 63) >= band);
+            } else {
+                interior = jbase >= R + 64 + wp && jbase + 63 <= n - 1;
+            }
             int lo_v = 0, hi_v = 64;
             uint64_t vmask = ~0ull;
             uint64_t X = mk64(xlo, xhi);
             if (!interior) {
-                // Valid cells of this row: columns [i + wp, n-1], rows < n.
-                lo_v = i + wp - jbase;
-                lo_v = lo_v < 0 ? 0 : lo_v;
-                if (i >= n || lo_v > 64) lo_v = 64;
-                hi_v = n - jbase;
-                hi_v = hi_v > 64 ? 64 : hi_v;
-                vmask = lo_v < hi_v ? range_mask(lo_v, hi_v) : 0ull;
+                if constexpr (FULL) {
+                    // Valid cells of this row: columns [0, nb) outside the band.
+                    vmask = 0ull;
+                    if (i < n) {
+                        const int hv = nb - jbase < 64 ? nb - jbase : 64;
+                        vmask = hv > 0 ? range_mask(0, hv) : 0ull;
+                        if (band > 0) {
+                            int64_t blo = (int64_t)i - band + 1 - jbase, bhi = (int64_t)i + band - jbase;
+                            blo = blo < 0 ? 0 : blo;
+                            bhi = bhi > 64 ? 64 : bhi;
+                            if (blo < bhi) vmask &= ~range_mask((uint32_t)blo, (uint32_t)bhi);
+                        }
+                    }
+                } else {
+                    // Valid cells of this row: columns [i + wp, n-1], rows < n.
+                    lo_v = i + wp - jbase;
+                    lo_v = lo_v < 0 ? 0 : lo_v;
+                    if (i >= n || lo_v > 64) lo_v = 64;
+                    hi_v = n - jbase;
+                    hi_v = hi_v > 64 ? 64 : hi_v;
+                    vmask = lo_v < hi_v ? range_mask(lo_v, hi_v) : 0ull;
+                }
                 X &= vmask;
                 xlo = (uint32_t)X;
                 xhi = (uint32_t)(X >> 32);
@@ -492,19 +581,27 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
 
             const bool any = __ballot(X != 0ull) != 0ull;
 
+            // This tile's carries from the wave above, and a free slot below.
+            // After one wait has given up the wave stops waiting (the job is
+            // flagged as failed), so a strip finishes in bounded time.
+            if (wave > 0 && sync_ok) sync_ok = wait_counter(&L.prod[wave - 1], t + 1);
+            if (wave < nw - 1 && sync_ok) sync_ok = wait_counter(&L.cons[wave], t - kRing + 1);
+
             if (interior && !any) {
                 // No recurrence in an interior tile: every open run sees 64
                 // white cells.  Only carried states change; a black run that
                 // was open ends at the tile's first cell.
-                if (hs.color) {
-                    finish_run<kHoriz>(hctx, 1u, hs.len, hs.first);
-                    hs = Run{0u, 64u, 0u};
-                } else {
-                    hs.len += 64u;
+                if constexpr (!FULL) {
+                    if (hs.color) {
+                        finish_run<kHoriz>(hctx, 1u, hs.len, hs.first);
+                        hs = Run{0u, 64u, 0u};
+                    } else {
+                        hs.len += 64u;
+                    }
                 }
                 {
-                    Run st = wave == 0 ? Run{0u, 0u, 1u} : unpack_run(L.vs((step - 1) & 1, wave - 1, lane));
-                    const int64_t sidx = soff + (jbase + lane - R0 - wp);
+                    Run st = wave == 0 ? Run{0u, 0u, 1u} : unpack_run(L.vs(slot, wave - 1, lane));
+                    const int64_t sidx = vbase + (jbase + lane);
                     if (st.color) {
                         const LineCtx lc{&j, bins, sidx, true, 0u};
                         finish_run<kVert>(lc, 1u, st.len, st.first);
@@ -517,7 +614,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                         j.vlast[sidx] = pk;
                         if (st.first) j.vfirst[sidx] = pk;
                     } else {
-                        L.vs(step & 1, wave, lane) = pack_run(st);
+                        L.vs(slot, wave, lane) = pack_run(st);
                     }
                 }
                 {
@@ -527,60 +624,65 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                     const int klo = kup - 64;
                     Run up;
                     if (wave == 0) {
-                        j.dfirst[soff + (kup - wp)] = 0;   // white first cell
+                        if (!FULL || dok(kup)) j.dfirst[dbase + kup] = 0;   // white first cell
                         up = Run{0u, 0u, 0u};
                     } else {
-                        up = unpack_run(L.ds((step - 1) & 1, wave - 1, lane));
+                        up = unpack_run(L.ds(slot, wave - 1, lane));
                     }
                     if (up.color) {
-                        const LineCtx lc{&j, bins, soff + (kup - wp), true, 0u};
-                        finish_run<kDiag>(lc, 1u, up.len, up.first);
+                        const LineCtx lc{&j, bins, dbase + kup, true, 0u};
+                        finish_run<kDiag, kDW>(lc, 1u, up.len, up.first);
                         up = Run{0u, 0u, 0u};
                     }
                     // Lane 0's lower part is empty (its diagonal left this wave
                     // at the previous tile's corner): its run goes on unchanged.
                     Run lw = left;
                     if (lw.color && lane != 0) {
-                        const LineCtx lc{&j, bins, soff + (klo - wp), true, 0u};
-                        finish_run<kDiag>(lc, 1u, lw.len, lw.first);
+                        const LineCtx lc{&j, bins, dbase + klo, !FULL || dok(klo), 0u};
+                        finish_run<kDiag, kDW>(lc, 1u, lw.len, lw.first);
                         lw = Run{0u, 0u, 0u};
                     }
                     if (wave < nw - 1) {
-                        L.ds(step & 1, wave, lane) = pack_run(lw);
-                    } else {
+                        L.ds(slot, wave, lane) = pack_run(lw);
+                    } else if (!FULL || dok(klo)) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        j.dlast[soff + (klo - wp)] = b;
-                        if (lw.first) j.dfirst[soff + (klo - wp)] = b;
+                        j.dlast[dbase + klo] = b;
+                        if (lw.first) j.dfirst[dbase + klo] = b;
                     }
                     left = up;
                 }
-                __syncthreads();
+                if (wave > 0) publish_counter(&L.cons[wave - 1], t + 1);
+                if (wave < nw - 1) publish_counter(&L.prod[wave], t + 1);
                 continue;
             }
 
             // ---- horizontal runs (row i of U) ----
-            if (lo_v < hi_v) {
-                if (!hstarted) {
-                    hstarted = true;
-                    hs = Run{(uint32_t)((X >> lo_v) & 1ull), 0u, 1u};
+            if constexpr (!FULL) {
+                if (lo_v < hi_v) {
+                    if (!hstarted) {
+                        hstarted = true;
+                        hs = Run{(uint32_t)((X >> lo_v) & 1ull), 0u, 1u};
+                    }
+                    run_segment<kHoriz>(X, vmask, (uint32_t)lo_v, (uint32_t)hi_v, hs, hctx);
                 }
-                run_segment<kHoriz>(X, vmask, (uint32_t)lo_v, (uint32_t)hi_v, hs, hctx);
             }
 
-            // ---- vertical runs (columns of U) ----
+            // ---- vertical runs (columns) ----
             {
                 uint32_t ylo = xlo, yhi = xhi;
                 if (any) transpose64(ylo, yhi, lane);
                 else { ylo = 0; yhi = 0; }
                 const uint64_t Y = mk64(ylo, yhi);
                 const int jc = jbase + lane;
-                const int e = interior ? 64 : jc - wp - R;   // last valid local row of column jc
-                if (interior || (jc <= n - 1 && e >= 0)) {
+                // last valid local row of column jc: the band (auto) or the
+                // bottom border (full) ends its segment
+                const int e = interior ? 64 : (FULL ? n - 1 - R : jc - wp - R);
+                if (interior || (jc <= nb - 1 && e >= 0)) {
                     const uint32_t vhi = e >= 63 ? 64u : (uint32_t)(e + 1);
                     Run st;
                     if (wave == 0) st = Run{(uint32_t)(Y & 1ull), 0u, 1u};
-                    else st = unpack_run(L.vs((step - 1) & 1, wave - 1, lane));
-                    const int64_t sidx = soff + (jc - R0 - wp);
+                    else st = unpack_run(L.vs(slot, wave - 1, lane));
+                    const int64_t sidx = vbase + jc;
                     LineCtx lc{&j, bins, sidx, true, 0u};
                     const uint64_t vwin = vhi >= 64 ? ~0ull : ((1ull << vhi) - 1ull);
                     run_segment<kVert>(Y, vwin, 0u, vhi, st, lc);
@@ -589,7 +691,7 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                         j.vlast[sidx] = pk;
                         if (st.first) j.vfirst[sidx] = pk;
                     } else {
-                        L.vs(step & 1, wave, lane) = pack_run(st);
+                        L.vs(slot, wave, lane) = pack_run(st);
                     }
                 }
             }
@@ -617,55 +719,60 @@ __device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
                     // does not matter).
                     up = Run{(uint32_t)(D & 1ull), 0u, 1u};
                     if (!up.color) {
-                        if (kup >= wp && kup <= n - 1 - R0) j.dfirst[soff + (kup - wp)] = 0;
+                        if (dok(kup)) j.dfirst[dbase + kup] = 0;
                         up.first = 0;
                     }
-                } else if (jbase + q > n - 1) {
+                } else if (jbase + q > nb - 1) {
                     up = Run{0u, 0u, 0u};   // starts past the border
                 } else {
-                    up = unpack_run(L.ds((step - 1) & 1, wave - 1, lane));
+                    up = unpack_run(L.ds(slot, wave - 1, lane));
                 }
                 {
-                    const bool ok = kup >= wp && kup <= n - 1 - R0;
-                    LineCtx lc{&j, bins, soff + (kup - wp), ok, 0u};
-                    run_segment<kDiag>(D, upwin, 0u, (uint32_t)(64 - q), up, lc);
+                    LineCtx lc{&j, bins, dbase + kup, dok(kup), 0u};
+                    run_segment<kDiag, kDW>(D, upwin, 0u, (uint32_t)(64 - q), up, lc);
                 }
                 Run lw = left;
                 {
-                    const bool ok = klo >= wp && klo <= n - 1 - R0;
-                    LineCtx lc{&j, bins, soff + (klo - wp), ok, 0u};
-                    run_segment<kDiag>(D, ~upwin, (uint32_t)(64 - q), 64u, lw, lc);
+                    const bool ok = dok(klo);
+                    LineCtx lc{&j, bins, dbase + klo, ok, 0u};
+                    run_segment<kDiag, kDW>(D, ~upwin, (uint32_t)(64 - q), 64u, lw, lc);
                     // The lower part ends on row R+63.  Diagonals with no cell on
-                    // the next row end here at the right border; the others go to
-                    // the wave below or, from the last wave, into the summary.
-                    if (R + 64 + klo > n - 1) {
-                        if (lw.color || lw.first) finish_run<kDiag>(lc, lw.color, lw.len, lw.first);
+                    // the next row end here at the right (or, full matrix,
+                    // bottom) border; the others go to the wave below or, from
+                    // the last wave, into the summary.
+                    const bool ends = FULL ? (R + 64 > n - 1 || R + 64 + klo > nb - 1)
+                                           : (R + 64 + klo > n - 1);
+                    if (ends) {
+                        if (lw.color || lw.first) finish_run<kDiag, kDW>(lc, lw.color, lw.len, lw.first);
                     } else if (wave < nw - 1) {
-                        L.ds(step & 1, wave, lane) = pack_run(lw);
+                        L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (ok) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        j.dlast[soff + (klo - wp)] = b;
-                        if (lw.first) j.dfirst[soff + (klo - wp)] = b;
+                        j.dlast[dbase + klo] = b;
+                        if (lw.first) j.dfirst[dbase + klo] = b;
                     }
                 }
                 left = up;
             }
         }
-        __syncthreads();
+        if (wave > 0) publish_counter(&L.cons[wave - 1], t + 1);
+        if (wave < nw - 1) publish_counter(&L.prod[wave], t + 1);
     }
+    if (!sync_ok) atomicOr(j.flag, 8);   // a neighbour wait gave up: result invalid
 
     if (wave_has_u) {
         // Rows end at column n-1: their last run is complete.
-        if (hstarted) finish_run<kHoriz>(hctx, hs.color, hs.len, hs.first);
+        if constexpr (!FULL) {
+            if (hstarted) finish_run<kHoriz>(hctx, hs.color, hs.len, hs.first);
+        }
         // Upper parts that left the last tile on its right edge end at the border.
         const int kup = j.c_last * 64 + lane - R;
-        const bool ok = kup >= wp && kup <= n - 1 - R0;
-        LineCtx lc{&j, bins, soff + (kup - wp), ok, 0u};
-        if (left.color || left.first) finish_run<kDiag>(lc, left.color, left.len, left.first);
+        LineCtx lc{&j, bins, dbase + kup, dok(kup), 0u};
+        if (left.color || left.first) finish_run<kDiag, kDW>(lc, left.color, left.len, left.first);
     }
 }
 
-template <int NORM, int M>
+template <int NORM, int M, int MODE>
 __global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_tiles(const JobDesc *__restrict__ jobs, const GroupDesc *__restrict__ groups, int g,
         int *counters) {
@@ -676,8 +783,10 @@ k_tiles(const JobDesc *__restrict__ jobs, const GroupDesc *__restrict__ groups, 
     L.bv = L.bd + kCapD;
     L.bw = L.bv + kCapV;
     L.vslot = L.bw + kCapW;
-    L.dslot = L.vslot + 2 * nw * 64;
-    L.item = reinterpret_cast<int *>(L.dslot + 2 * nw * 64);
+    L.dslot = L.vslot + kRing * nw * 64;
+    L.prod = reinterpret_cast<int *>(L.dslot + kRing * nw * 64);
+    L.cons = L.prod + kMaxWaves;
+    L.item = L.cons + kMaxWaves;
     L.nw = nw;
     const GroupDesc gd = groups[g];
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
@@ -688,6 +797,7 @@ k_tiles(const JobDesc *__restrict__ jobs, const GroupDesc *__restrict__ groups, 
     __syncthreads();
     while (true) {
         if (threadIdx.x == 0) *L.item = atomicAdd(counters + g, 1);
+        if (threadIdx.x < 2 * kMaxWaves) L.prod[threadIdx.x] = 0;   // prod and cons
         __syncthreads();
         const int item = *L.item;
         __syncthreads();
@@ -699,7 +809,7 @@ k_tiles(const JobDesc *__restrict__ jobs, const GroupDesc *__restrict__ groups, 
             if (jobs[mid].strip_base <= item) lo = mid; else hi = mid - 1;
         }
         const JobDesc j = jobs[lo];
-        process_strip<NORM, M>(j, item - j.strip_base, L);
+        process_strip<NORM, M, MODE>(j, item - j.strip_base, L);
         __syncthreads();
         flush_bins(L, j);
         __syncthreads();
@@ -721,8 +831,49 @@ struct StitchLds {
 __device__ __forceinline__ void emit_line(StitchLds &L, const JobDesc &j, uint32_t color,
                                           uint32_t len) {
     if (len == 0) return;
-    if (color) emit(L.bv, kCapV, j.hv, len, 1u, (uint32_t)j.n, j.flag);
-    else emit(L.bw, kCapW, j.hw, len, 1u, (uint32_t)j.n, j.flag);
+    if (color) emit(L.bv, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
+    else emit(L.bw, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
+}
+
+// Stitch of a full (not symmetric) matrix: lines [0, nb) are the columns, lines
+// [nb, nb + n + nb - 1) the diagonals k = -(n-1) .. nb-1.  A diagonal that
+// starts inside a strip (at the left border) has no top-edge summary there.
+__device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
+    const int n = j.n, nb = j.nb, H = j.H, S = j.nstrips;
+    if (line < nb) {
+        const int col = (int)line;
+        uint32_t oc = 0, ol = 0;
+        for (int s = 0; s < S; ++s) {
+            const uint32_t Ls = s < S - 1 ? (uint32_t)H : (uint32_t)(n - s * H);
+            const int64_t idx = (int64_t)s * nb + col;
+            const uint32_t f = j.vfirst[idx], l = j.vlast[idx];
+            const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
+            if (fl == Ls) {   // the segment is one run
+                if (ol && oc == fc) ol += Ls;
+                else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
+            } else {
+                if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
+                else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
+                oc = l >> 15;
+                ol = l & 0x7FFFu;
+            }
+        }
+        emit_line(L, j, oc, ol);
+    } else if (line < (int64_t)nb + n + nb - 1) {
+        const int k = (int)(line - nb) - (n - 1);
+        const int r0 = k < 0 ? -k : 0;                              // first row
+        const int r1 = n - 1 < nb - 1 - k ? n - 1 : nb - 1 - k;     // last row
+        const int sf = r0 / H, sl = r1 / H;
+        uint32_t open = 0;
+        for (int s = sf; s <= sl; ++s) {
+            const int64_t idx = (int64_t)s * (nb + H - 1) + (k + s * H + H - 1);
+            const bool top = s > sf || r0 == s * H;
+            const uint32_t fb = top ? (uint32_t)j.dfirst[idx] : 0u;
+            if (s < sl && top && fb == (uint32_t)H) { open += H; continue; }
+            if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 1u, (uint32_t)j.hmax, j.flag);
+            open = s < sl ? (uint32_t)j.dlast[idx] : 0u;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__restrict__ jobs,
@@ -743,7 +894,9 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
     const int n = j.n, wp = j.wp, H = j.H;
     const int64_t line = (int64_t)(blockIdx.x - j.stitch_block0) * blockDim.x + threadIdx.x;
 
-    if (line < n) {
+    if (j.mode != kModeAuto) {
+        stitch_full(L, j, line);
+    } else if (line < n) {
         // ---- column j of the full matrix ----
         const int col = (int)line;
         uint32_t oc = 0, ol = 0;   // open run after folding column `col` of U
@@ -820,7 +973,7 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
 // lengths.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void chunk_of(const JobDesc &j, int b, int64_t &lo, int64_t &hi) {
-    const int64_t len = (int64_t)j.n + 1;
+    const int64_t len = (int64_t)j.hmax + 1;
     const int64_t per = (len + j.stat_blocks - 1) / j.stat_blocks;
     lo = (int64_t)b * per;
     hi = lo + per < len ? lo + per : len;
@@ -918,32 +1071,41 @@ __global__ void k_stats_final(const JobDesc *__restrict__ jobs, int njobs) {
 // ---------------------------------------------------------------------------
 using TileKernel = void (*)(const JobDesc *, const GroupDesc *, int, int *);
 
-template <int NORM>
+template <int NORM, int MODE>
 TileKernel pick_kernel(int m) {
     switch (m) {
-        case 1: return k_tiles<NORM, 1>;
-        case 2: return k_tiles<NORM, 2>;
-        case 3: return k_tiles<NORM, 3>;
-        case 4: return k_tiles<NORM, 4>;
-        case 5: return k_tiles<NORM, 5>;
-        case 6: return k_tiles<NORM, 6>;
-        default: return k_tiles<NORM, 0>;
+        case 1: return k_tiles<NORM, 1, MODE>;
+        case 2: return k_tiles<NORM, 2, MODE>;
+        case 3: return k_tiles<NORM, 3, MODE>;
+        case 4: return k_tiles<NORM, 4, MODE>;
+        case 5: return k_tiles<NORM, 5, MODE>;
+        case 6: return k_tiles<NORM, 6, MODE>;
+        default: return k_tiles<NORM, 0, MODE>;
     }
 }
 
-TileKernel tile_kernel(int norm, int m) {
-    if (norm == RQA_NORM_L1) return pick_kernel<RQA_NORM_L1>(m);
-    if (norm == RQA_NORM_L2) return pick_kernel<RQA_NORM_L2>(m);
-    return pick_kernel<RQA_NORM_LINF>(m);
+template <int MODE>
+TileKernel tile_kernel_mode(int norm, int m) {
+    if (norm == RQA_NORM_L1) return pick_kernel<RQA_NORM_L1, MODE>(m);
+    if (norm == RQA_NORM_L2) return pick_kernel<RQA_NORM_L2, MODE>(m);
+    return pick_kernel<RQA_NORM_LINF, MODE>(m);
+}
+
+TileKernel tile_kernel(int mode, int norm, int m) {
+    if (mode == kModeMatrix) return k_tiles<RQA_NORM_LINF, 1, kModeMatrix>;   // no predicate
+    if (mode == kModeCross) return tile_kernel_mode<kModeCross>(norm, m);
+    return tile_kernel_mode<kModeAuto>(norm, m);
 }
 
 int group_key(const Job &jb) {
-    return (jb.kp.norm * 16 + (jb.kp.m <= kMaxM ? jb.kp.m : 0)) * 32 + jb.waves;
+    const int nm = jb.mode == kModeMatrix ? 0 : jb.kp.norm * 16 + (jb.kp.m <= kMaxM ? jb.kp.m : 0);
+    return ((jb.mode * 64) + nm) * 32 + jb.waves;
 }
 
 struct Layout {
     int H, nstrips;
-    int64_t entries;       // summary entries per array
+    int64_t ventries;      // vertical summary entries per array (first, last)
+    int64_t dentries;      // diagonal summary entries per array
     int64_t tail_len;
     size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, bytes;
 };
@@ -962,20 +1124,29 @@ Layout layout_of(const Job &jb) {
     const int64_t n = jb.n_vec;
     const int wp = jb.kp.theiler > 1 ? jb.kp.theiler : 1;
     L.H = 64 * (jb.waves > 0 ? jb.waves : default_waves_impl(n));
-    L.nstrips = n - wp > 0 ? (int)((n - wp + L.H - 1) / L.H) : 0;
-    // sum over strips of (n - wp - s H) entries
-    L.entries = (int64_t)L.nstrips * (n - wp) - (int64_t)L.H * ((int64_t)L.nstrips * (L.nstrips - 1) / 2);
-    if (L.entries < 1) L.entries = 1;
-    const int64_t c_last = (n - 1) / 64;
-    L.tail_len = 64 + (int64_t)(jb.kp.m - 1) * jb.kp.tau;
-    (void)c_last;
+    if (jb.mode == kModeAuto) {
+        L.nstrips = n - wp > 0 ? (int)((n - wp + L.H - 1) / L.H) : 0;
+        // sum over strips of (n - wp - s H) entries
+        L.ventries = (int64_t)L.nstrips * (n - wp) -
+                     (int64_t)L.H * ((int64_t)L.nstrips * (L.nstrips - 1) / 2);
+        L.dentries = L.ventries;
+    } else {
+        const int64_t nb = jb.n_cols;
+        L.nstrips = (int)((n + L.H - 1) / L.H);
+        L.ventries = (int64_t)L.nstrips * nb;
+        L.dentries = (int64_t)L.nstrips * (nb + L.H - 1);
+    }
+    if (L.ventries < 1) L.ventries = 1;
+    if (L.dentries < 1) L.dentries = 1;
+    L.tail_len = jb.mode == kModeMatrix ? 0 : 64 + (int64_t)(jb.kp.m - 1) * jb.kp.tau;
+    const int64_t lead = jb.mode == kModeAuto ? n : 1;
     size_t off = 0;
     L.off_tail = off; off += a256(sizeof(float) * (size_t)L.tail_len);
-    L.off_lead = off; off += a256(sizeof(uint32_t) * (size_t)n);
-    L.off_vf = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
-    L.off_vl = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
-    L.off_df = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
-    L.off_dl = off; off += a256(sizeof(uint16_t) * (size_t)L.entries);
+    L.off_lead = off; off += a256(sizeof(uint32_t) * (size_t)lead);
+    L.off_vf = off; off += a256(sizeof(uint16_t) * (size_t)L.ventries);
+    L.off_vl = off; off += a256(sizeof(uint16_t) * (size_t)L.ventries);
+    L.off_df = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
+    L.off_dl = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
     L.off_ent = off; off += a256(sizeof(double) * 3 * kStatMaxBlocks);
     L.bytes = off;
     return L;
@@ -1075,11 +1246,18 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         hgroups[ngroups - 1].job1 = r + 1;
         char *scr = static_cast<char *>(jb.scratch);
         JobDesc d{};
+        const bool full = jb.mode != kModeAuto;
+        const int64_t hlen = jb.hist_len();
+        const int64_t ncols = full ? jb.n_cols : jb.n_vec;
         d.s = jb.series;
+        d.sb = jb.mode == kModeCross ? jb.series_b : jb.series;
+        d.n_points_b = jb.mode == kModeCross ? jb.n_points_b : jb.n_points;
+        d.bits = jb.bits;
+        d.words = jb.words;
         d.tail = reinterpret_cast<const float *>(scr + lay.off_tail);
         d.hd = reinterpret_cast<unsigned long long *>(jb.hist);
-        d.hv = d.hd + (jb.n_vec + 1);
-        d.hw = d.hv + (jb.n_vec + 1);
+        d.hv = d.hd + hlen;
+        d.hw = d.hv + hlen;
         d.flag = jb.flag;
         d.lead = reinterpret_cast<uint32_t *>(scr + lay.off_lead);
         d.vfirst = reinterpret_cast<uint16_t *>(scr + lay.off_vf);
@@ -1088,6 +1266,9 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         d.dlast = reinterpret_cast<uint16_t *>(scr + lay.off_dl);
         d.n_points = jb.n_points;
         d.n = (int32_t)jb.n_vec;
+        d.nb = (int32_t)ncols;
+        d.hmax = (int32_t)(hlen - 1);
+        d.mode = jb.mode;
         d.m = kp.m;
         d.tau = kp.tau;
         d.norm = kp.norm;
@@ -1096,18 +1277,19 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         d.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
         d.H = lay.H;
         d.nstrips = lay.nstrips;
-        d.c_last = (int32_t)((jb.n_vec - 1) / 64);
+        d.c_last = (int32_t)((ncols - 1) / 64);
         d.tail_len = (int32_t)lay.tail_len;
         d.strip_base = strip_acc;
         d.stitch_block0 = stitch_blocks;
         d.mins[0] = kp.lmin;
         d.mins[1] = kp.vmin;
         d.mins[2] = kp.wmin;
-        d.stat_blocks = (int32_t)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (jb.n_vec + 1 + 8191) / 8192));
+        d.stat_blocks = (int32_t)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (hlen + 8191) / 8192));
         d.stats = reinterpret_cast<JobStats *>(reinterpret_cast<char *>(jb.flag) + 8);
         d.ent_part = reinterpret_cast<double *>(scr + lay.off_ent);
         strip_acc += lay.nstrips;
-        stitch_blocks += (int)((2 * jb.n_vec + kStitchThreads - 1) / kStitchThreads);
+        const int64_t lines = full ? ncols + jb.n_vec + ncols - 1 : 2 * jb.n_vec;
+        stitch_blocks += (int)((lines + kStitchThreads - 1) / kStitchThreads);
         hdesc[r] = d;
     }
     hgroups[ngroups - 1].items = strip_acc;
@@ -1134,7 +1316,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         if (gd.items == 0) continue;
         const KParams &kp = jobs_in[order[gd.job0]].kp;
         const int w = jobs_in[order[gd.job0]].waves;
-        TileKernel kern = tile_kernel(kp.norm, kp.m);
+        TileKernel kern = tile_kernel(jobs_in[order[gd.job0]].mode, kp.norm, kp.m);
         int occ = 0;
         const size_t lds = strip_lds_bytes(w);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * w, lds) != hipSuccess ||

@@ -89,6 +89,19 @@ def _device_series(series):
     return series
 
 
+def _device_bits(bits):
+    import torch
+    if not isinstance(bits, torch.Tensor):
+        raise TypeError("bits must be a torch tensor on the GPU")
+    if not bits.is_cuda:
+        raise ValueError("bits must live in device memory (a CUDA/HIP tensor)")
+    if bits.dtype not in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        raise ValueError("bits must be a 64-bit integer tensor")
+    if bits.dim() != 2 or not bits.is_contiguous():
+        raise ValueError("bits must be a contiguous 2-D tensor (rows, words)")
+    return bits
+
+
 def _stream_ptr(stream):
     import torch
     if stream is None:
@@ -121,7 +134,7 @@ class RQA:
         self._h = h
         self._keep = None
         self._count = 0
-        self._nvec = []
+        self._hlen = []     # histogram entries per job of the last run
 
     @classmethod
     def from_params(cls, p):
@@ -170,7 +183,7 @@ class RQA:
               "rqa_run")
         self._keep = s
         self._count = 1
-        self._nvec = [self.hist_len(s.numel()) - 1]
+        self._hlen = [self.hist_len(s.numel())]
         return self
 
     def result(self, histograms: bool = True) -> RQAResult:
@@ -193,28 +206,64 @@ class RQA:
                                   _stream_ptr(stream)), "rqa_run_batch")
         self._keep = s
         self._count = len(off)
-        self._nvec = [int(L) - (self.params.m - 1) * self.params.tau for L in ln]
+        self._hlen = [int(L) - (self.params.m - 1) * self.params.tau + 1 for L in ln]
         return self
+
+    def run_cross(self, a, b, stream=None):
+        """Enqueue the cross recurrence RQA of device series a (rows) and b
+        (columns) (asynchronous)."""
+        sa, sb = _device_series(a), _device_series(b)
+        check(lib().rqa_run_cross(self._h, ctypes.c_void_p(sa.data_ptr()), sa.numel(),
+                                  ctypes.c_void_p(sb.data_ptr()), sb.numel(),
+                                  _stream_ptr(stream)), "rqa_run_cross")
+        out = ctypes.c_int64()
+        check(lib().rqa_cross_hist_len(self._h, sa.numel(), sb.numel(), ctypes.byref(out)),
+              "rqa_cross_hist_len")
+        self._keep = (sa, sb)
+        self._count = 1
+        self._hlen = [out.value]
+        return self
+
+    def cross(self, a, b, stream=None) -> RQAResult:
+        self.run_cross(a, b, stream)
+        return self.result()
+
+    def run_matrix(self, bits, n_cols: int, stream=None):
+        """Enqueue the RQA of a given binary matrix: ``bits`` is a device int64
+        tensor of shape (n_rows, words), bit b of word c of row i = cell
+        (i, 64c+b) (asynchronous)."""
+        B = _device_bits(bits)
+        n_rows, words = B.shape
+        check(lib().rqa_run_matrix(self._h, ctypes.c_void_p(B.data_ptr()), int(n_rows),
+                                   int(n_cols), int(words), _stream_ptr(stream)), "rqa_run_matrix")
+        self._keep = B
+        self._count = 1
+        self._hlen = [max(int(n_rows), int(n_cols)) + 1]
+        return self
+
+    def matrix(self, bits, n_cols: int, stream=None) -> RQAResult:
+        self.run_matrix(bits, n_cols, stream)
+        return self.result()
 
     def result_batch(self, index: int, histograms: bool = True) -> RQAResult:
         return self._fetch(int(index), histograms)
 
     def _fetch(self, index, histograms):
-        n = self._nvec[0 if index is None else index] if self._nvec else 0
+        hl = self._hlen[0 if index is None else index] if self._hlen else 0
         ms = RqaMeasures()
-        if histograms and n > 0:
-            d = np.empty(n + 1, dtype=np.uint64)   # filled completely by the library
-            v = np.empty(n + 1, dtype=np.uint64)
-            w = np.empty(n + 1, dtype=np.uint64)
+        if histograms and hl > 1:
+            d = np.empty(hl, dtype=np.uint64)   # filled completely by the library
+            v = np.empty(hl, dtype=np.uint64)
+            w = np.empty(hl, dtype=np.uint64)
             ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in (d, v, w)]
         else:
             d = v = w = None
             ptrs = [None, None, None]
         if index is None:
-            rc = lib().rqa_result(self._h, ctypes.byref(ms), *ptrs, n + 1)
+            rc = lib().rqa_result(self._h, ctypes.byref(ms), *ptrs, hl)
             check(rc, "rqa_result")
         else:
-            rc = lib().rqa_result_batch(self._h, index, ctypes.byref(ms), *ptrs, n + 1)
+            rc = lib().rqa_result_batch(self._h, index, ctypes.byref(ms), *ptrs, hl)
             check(rc, "rqa_result_batch")
         return RQAResult(_measures_dict(ms), d, v, w, int(ms.n_vec), int(ms.n_rec))
 
