@@ -150,6 +150,26 @@ int rqa_cross_hist_len(const rqa_handle *h, int64_t na_points, int64_t nb_points
 int rqa_run_matrix(rqa_handle *h, const uint64_t *d_bits, int64_t n_rows, int64_t n_cols,
                    int64_t words_per_row, void *hip_stream);
 
+/* Recurrence plot output (Sect. 4: the approach also produces recurrence
+ * plots; Sect. 7 workflow: RecurrencePlotComputation / RecurrencePlotResult).
+ * Writes the n x n recurrence matrix of the series under h's embedding, norm,
+ * radius and Theiler window (cells |i-j| < theiler are 0) into caller-owned
+ * DEVICE memory d_bits: row-major, words_per_row (>= ceil(n/64)) 64-bit words
+ * per row, bit b of word c of row i = cell (i, 64c+b); bits past column n-1 are
+ * 0 and words past ceil(n/64) are left unchanged.  n*words_per_row*8 bytes
+ * (125 MB at n = 100,000): meant for small series and windows.  The output can
+ * be fed back to rqa_run_matrix.  Asynchronous on hip_stream; the caller keeps
+ * d_series and d_bits alive until the stream has passed the call.
+ * RQA_ESIZE if words_per_row is too small, RQA_ETOOSHORT as rqa_run. */
+int rqa_plot(rqa_handle *h, const float *d_series, int64_t n_points, uint64_t *d_bits,
+             int64_t words_per_row, void *hip_stream);
+
+/* Cross recurrence plot: the n_a x n_b matrix of rqa_run_cross, packed as by
+ * rqa_plot (words_per_row >= ceil(n_b/64)). */
+int rqa_plot_cross(rqa_handle *h, const float *d_a, int64_t na_points, const float *d_b,
+                   int64_t nb_points, uint64_t *d_bits, int64_t words_per_row,
+                   void *hip_stream);
+
 /* Batched windowed RQA (many windows of uneven length over one device series,
  * one persistent launch; the RQA X "epochs" idea of Sect. 3 run in parallel).
  * offsets/lengths: count host int64 values, copied during the call; window w

@@ -11,6 +11,7 @@ it.  It shares no code with the HIP implementation.
 * ``cross_histograms`` / ``cross_measures`` -- cross recurrence of two series
   (rows: series a, columns: series b; 2N-1 diagonals, each run once).
 * ``matrix_histograms`` -- the same histograms of a given bit matrix.
+* ``plot`` -- the masked recurrence (or cross recurrence) matrix, bit-packed.
 * ``brute``      -- an independent pure-Python brute force that materialises the
   whole matrix for tiny inputs; it pins the C code.
 """
@@ -71,6 +72,11 @@ def _load():
         lib.rqa_oracle_rect_measures.argtypes = [
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.rqa_oracle_plot.restype = ctypes.c_int
+        lib.rqa_oracle_plot.argtypes = [
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+            ctypes.c_int, ctypes.c_float, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+            ctypes.c_int64]
         lib.rqa_oracle_n_vectors.restype = ctypes.c_int64
         lib.rqa_oracle_n_vectors.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int]
         _lib = lib
@@ -180,3 +186,25 @@ def cross_rqa(a, b, params, threads: int = 0):
     nb = n_vectors(len(b), params.m, params.tau)
     return (d, v, w), rect_measures(d, v, w, na, nb, params.theiler, params.lmin, params.vmin,
                                     params.wmin)
+
+
+def plot(a, params, b=None, words: int | None = None):
+    """The masked recurrence matrix of series a (or the cross matrix of a and b)
+    packed row-major: uint64 array (rows, words), bit b of word c of row i =
+    cell (i, 64c+b)."""
+    sa = np.ascontiguousarray(a, dtype=np.float32)
+    sb = None if b is None else np.ascontiguousarray(b, dtype=np.float32)
+    na = n_vectors(len(sa), params.m, params.tau)
+    nb = na if sb is None else n_vectors(len(sb), params.m, params.tau)
+    if na < 1 or nb < 1:
+        raise ValueError("series too short for the embedding")
+    words = (nb + 63) // 64 if words is None else words
+    out = np.zeros((na, words), dtype=np.uint64)
+    rc = _load().rqa_oracle_plot(sa.ctypes.data, len(sa),
+                                 None if sb is None else sb.ctypes.data,
+                                 0 if sb is None else len(sb), params.m, params.tau,
+                                 float(np.float32(params.eps)), params.norm, params.theiler,
+                                 out.ctypes.data, words)
+    if rc != 0:
+        raise ValueError("invalid oracle arguments")
+    return out

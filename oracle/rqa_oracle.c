@@ -382,6 +382,41 @@ int rqa_oracle_matrix_histograms(const uint64_t *bits, int64_t n_rows, int64_t n
     return 0;
 }
 
+/* Recurrence plot (Sect. 4 and the workflow classes of Sect. 7): the
+ * masked matrix packed row-major, `words` 64-bit words per row, bit b of word c
+ * of row i = cell (i, 64c+b); bits past the last column are 0.  b == NULL: the
+ * n x n matrix of series a; otherwise the cross matrix of a (rows) and b
+ * (columns).  Returns 0, or -1 for invalid arguments. */
+int rqa_oracle_plot(const float *a, int64_t na_points, const float *b, int64_t nb_points, int m,
+                    int tau, float eps, int norm, int theiler, uint64_t *bits, int64_t words)
+{
+    oracle_rect r;
+    int64_t na, nb, i, j;
+    if (!a || !bits || m < 1 || tau < 1 || theiler < 0 || norm < 1 || norm > 3 ||
+        !(eps >= 0.0f) || isinf(eps))
+        return -1;
+    na = rqa_oracle_n_vectors(na_points, m, tau);
+    nb = b ? rqa_oracle_n_vectors(nb_points, m, tau) : na;
+    if (na < 1 || nb < 1 || words < (nb + 63) / 64)
+        return -1;
+    r.a = a;
+    r.b = b ? b : a;
+    r.m = m;
+    r.tau = tau;
+    r.norm = norm;
+    r.eps = eps;
+    r.eps_sq = eps * eps;
+    r.bits = NULL;
+    r.words = 0;
+    r.w = theiler;
+    memset(bits, 0, sizeof(uint64_t) * (size_t)(na * words));
+    for (i = 0; i < na; ++i)
+        for (j = 0; j < nb; ++j)
+            if (oracle_rect_cell(&r, i, j))
+                bits[i * words + (j >> 6)] |= (uint64_t)1 << (j & 63);
+    return 0;
+}
+
 /* Measure vector layout (all FP64):
  *  0 RR  1 DET  2 L  3 Lmax  4 DIV  5 L_entr  6 LAM  7 TT  8 Vmax  9 V_entr
  * 10 W  11 Wmax 12 W_entr 13 N_rec 14 n */

@@ -47,6 +47,8 @@ SIGNATURES = {
     "rqa_run_cross": (ctypes.c_int, [_P, _P, _I64, _P, _I64, _P]),
     "rqa_cross_hist_len": (ctypes.c_int, [_P, _I64, _I64, ctypes.POINTER(_I64)]),
     "rqa_run_matrix": (ctypes.c_int, [_P, _P, _I64, _I64, _I64, _P]),
+    "rqa_plot": (ctypes.c_int, [_P, _P, _I64, _P, _I64, _P]),
+    "rqa_plot_cross": (ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _I64, _P]),
     "rqa_result_batch": (ctypes.c_int, [_P, _I32, ctypes.POINTER(RqaMeasures), _P, _P, _P, _I64]),
     "rqa_measures_from_hist": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(RqaParams),
                                               ctypes.POINTER(RqaMeasures)]),

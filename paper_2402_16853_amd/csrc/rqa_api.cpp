@@ -179,6 +179,10 @@ struct rqa_handle {
     hipGraphExec_t graph = nullptr;
     void *graph_staging = nullptr;
     hipStream_t capture_stream = nullptr;
+    // recurrence plot output: tail scratch, and the event after the last plot
+    float *plot_tail = nullptr;
+    size_t plot_tail_bytes = 0;
+    hipEvent_t plot_done = nullptr;
 };
 
 namespace {
@@ -562,6 +566,57 @@ int rqa_run_matrix(rqa_handle *h, const uint64_t *d_bits, int64_t n_rows, int64_
     return enqueue_full(h, jb, hip_stream);
 }
 
+namespace {
+
+// Enqueue a recurrence plot; the tail scratch is reused, so a plot waits (on the
+// device) for the previous one of this handle.
+int plot(rqa_handle *h, const float *a, int64_t na_points, const float *b, int64_t nb_points,
+         uint64_t *d_bits, int64_t words, void *hip_stream) {
+    const KParams kp = make_kparams(h->p);
+    const int64_t d = static_cast<int64_t>(h->p.m - 1) * h->p.tau;
+    const int64_t na = na_points - d, nb = b ? nb_points - d : na;
+    if (na < 1 || nb < 1) return RQA_ETOOSHORT;
+    if (na > (int64_t(1) << 31) - 2 || nb > (int64_t(1) << 31) - 2) return RQA_EINVAL;
+    if (words < (nb + 63) / 64) return RQA_ESIZE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const size_t need = sizeof(float) * static_cast<size_t>(engine_plot_tail_floats(kp));
+    if (!h->plot_done && hipEventCreateWithFlags(&h->plot_done, hipEventDisableTiming) != hipSuccess)
+        return RQA_EDEVICE;
+    if (h->plot_tail_bytes < need) {
+        if (h->plot_tail) {
+            hipEventSynchronize(h->plot_done);
+            hipFree(h->plot_tail);
+        }
+        h->plot_tail = nullptr;
+        h->plot_tail_bytes = 0;
+        if (hipMalloc(&h->plot_tail, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return RQA_ENOMEM;
+        }
+        h->plot_tail_bytes = need;
+    } else if (hipStreamWaitEvent(st, h->plot_done, 0) != hipSuccess) {
+        return RQA_EDEVICE;
+    }
+    const int rc = engine_plot(kp, a, na_points, b, nb_points, d_bits, words, h->plot_tail, st);
+    if (rc != RQA_OK) return rc;
+    return hipEventRecord(h->plot_done, st) == hipSuccess ? RQA_OK : RQA_EDEVICE;
+}
+
+}  // namespace
+
+int rqa_plot(rqa_handle *h, const float *d_series, int64_t n_points, uint64_t *d_bits,
+             int64_t words_per_row, void *hip_stream) {
+    if (!h || !d_series || !d_bits || n_points < 0 || words_per_row < 1) return RQA_EINVAL;
+    return plot(h, d_series, n_points, nullptr, 0, d_bits, words_per_row, hip_stream);
+}
+
+int rqa_plot_cross(rqa_handle *h, const float *d_a, int64_t na_points, const float *d_b,
+                   int64_t nb_points, uint64_t *d_bits, int64_t words_per_row, void *hip_stream) {
+    if (!h || !d_a || !d_b || !d_bits || na_points < 0 || nb_points < 0 || words_per_row < 1)
+        return RQA_EINVAL;
+    return plot(h, d_a, na_points, d_b, nb_points, d_bits, words_per_row, hip_stream);
+}
+
 int rqa_result(rqa_handle *h, rqa_measures *out, uint64_t *diag, uint64_t *vert, uint64_t *white,
                int64_t hist_len) {
     if (h && h->has_run && h->batched) return RQA_ESTATE;
@@ -636,6 +691,11 @@ void rqa_destroy(rqa_handle *h) {
     if (h->capture_stream) hipStreamDestroy(h->capture_stream);
     if (h->host_cache) hipHostFree(h->host_cache);
     if (h->info_cache) hipHostFree(h->info_cache);
+    if (h->plot_done) {
+        hipEventSynchronize(h->plot_done);
+        hipEventDestroy(h->plot_done);
+    }
+    if (h->plot_tail) hipFree(h->plot_tail);
     delete h;
 }
 

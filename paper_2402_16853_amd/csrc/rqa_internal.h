@@ -119,6 +119,13 @@ int engine_launch(const std::vector<Job> &jobs, void *launch_scratch, void *stag
                   hipEvent_t staging_free, int groups, hipStream_t stream,
                   const PhaseEvents *phases = nullptr, AuxStreams *aux = nullptr);
 
+// Recurrence plot: the masked matrix of series a (b == nullptr) or the cross
+// matrix of a and b, bit-packed into `bits` (rows of `words` u64), on `stream`.
+// `tail` holds engine_plot_tail_floats(kp) device floats of scratch.
+int64_t engine_plot_tail_floats(const KParams &kp);
+int engine_plot(const KParams &kp, const float *a, int64_t na_points, const float *b,
+                int64_t nb_points, uint64_t *bits, int64_t words, float *tail, hipStream_t stream);
+
 // Host FP64 measures from histograms of length n+1.
 void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,
                         int64_t n, const rqa_params &p, rqa_measures *out);

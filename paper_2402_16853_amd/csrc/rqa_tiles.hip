@@ -1067,6 +1067,93 @@ __global__ void k_stats_final(const JobDesc *__restrict__ jobs, int njobs) {
 }
 
 // ---------------------------------------------------------------------------
+// Recurrence plot output: the masked matrix bit-packed row-major (bit b of word c
+// of row i = cell (i, 64c+b)).  A wave owns one 64-row tile row and a chunk of
+// column tiles.  For the matrix of one series only tiles on or above the
+// diagonal are evaluated; each one above it is also written transposed into the
+// mirror tile (the matrix is exactly symmetric).
+// ---------------------------------------------------------------------------
+struct PlotDesc {
+    const float *a;            // rows' series
+    const float *b;            // columns' series (one series: a)
+    const float *tail;         // coordinates of the last column tile, zero padded
+    uint64_t *bits;
+    int64_t words;             // 64-bit words per output row
+    int64_t nb_points;         // points of b
+    int32_t n, nb, m, tau, theiler;
+    float thr;
+    int32_t row_tiles, col_tiles, chunks, cross;
+    int32_t tail_len;
+};
+
+constexpr int kPlotChunk = 16;   // column tiles per wave
+
+__global__ void k_plot_tail(const PlotDesc d) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t base = (int64_t)(d.col_tiles - 1) * 64;
+    if (t < d.tail_len)
+        const_cast<float *>(d.tail)[t] = base + t < d.nb_points ? d.b[base + t] : 0.0f;
+}
+
+template <int NORM, int M>
+__global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+    const int r = wv / d.chunks, q = wv - r * d.chunks;
+    if (r >= d.row_tiles) return;
+    const int n = d.n, nb = d.nb, R = r * 64, i = R + lane;
+    const int irow = i < n ? i : n - 1;
+    const float *rowp = d.a + irow;
+    float xr[M > 0 ? M : 1];
+#pragma unroll
+    for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? rowp[(int64_t)k * d.tau] : 0.0f;
+    int cbeg = q * kPlotChunk;
+    const int cend = cbeg + kPlotChunk < d.col_tiles ? cbeg + kPlotChunk : d.col_tiles;
+    if (!d.cross && cbeg < r) cbeg = r;
+    const int64_t band = d.theiler;
+    for (int c = cbeg; c < cend; ++c) {
+        const int jbase = c * 64;
+        const ConstF cols = to_const(c == d.col_tiles - 1 ? d.tail : d.b + jbase);
+        uint32_t xlo, xhi;
+        tile_bits<NORM, M>(cols, d.tau, xr, rowp, d.m, d.thr, xlo, xhi);
+        uint64_t vm = 0ull;
+        if (i < n) {
+            const int hv = nb - jbase < 64 ? nb - jbase : 64;
+            vm = range_mask(0, (uint32_t)hv);
+            if (band > 0) {
+                int64_t blo = (int64_t)i - band + 1 - jbase, bhi = (int64_t)i + band - jbase;
+                blo = blo < 0 ? 0 : blo;
+                bhi = bhi > 64 ? 64 : bhi;
+                if (blo < bhi) vm &= ~range_mask((uint32_t)blo, (uint32_t)bhi);
+            }
+        }
+        const uint64_t X = mk64(xlo, xhi) & vm;
+        if (i < n) d.bits[(int64_t)i * d.words + c] = X;
+        if (!d.cross && c > r) {
+            uint32_t lo = (uint32_t)X, hi = (uint32_t)(X >> 32);
+            transpose64(lo, hi, lane);
+            const int jr = jbase + lane;   // row of the mirror tile
+            if (jr < n) d.bits[(int64_t)jr * d.words + r] = mk64(lo, hi);
+        }
+    }
+}
+
+using PlotKernel = void (*)(const PlotDesc);
+
+template <int NORM>
+PlotKernel pick_plot(int m) {
+    switch (m) {
+        case 1: return k_plot<NORM, 1>;
+        case 2: return k_plot<NORM, 2>;
+        case 3: return k_plot<NORM, 3>;
+        case 4: return k_plot<NORM, 4>;
+        case 5: return k_plot<NORM, 5>;
+        case 6: return k_plot<NORM, 6>;
+        default: return k_plot<NORM, 0>;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 using TileKernel = void (*)(const JobDesc *, const GroupDesc *, int, int *);
@@ -1349,6 +1436,40 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     hipLaunchKernelGGL(k_stats_entropy, dim3(kStatMaxBlocks, njobs), dim3(kStatThreads), 0, st, ddesc);
     hipLaunchKernelGGL(k_stats_final, dim3((3 * njobs + 255) / 256), dim3(256), 0, st, ddesc, njobs);
     if (phases) hipEventRecord(phases->ev[3], st);
+    return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
+}
+
+int64_t engine_plot_tail_floats(const KParams &kp) { return 64 + (int64_t)(kp.m - 1) * kp.tau; }
+
+int engine_plot(const KParams &kp, const float *a, int64_t na_points, const float *b,
+                int64_t nb_points, uint64_t *bits, int64_t words, float *tail, hipStream_t st) {
+    const int64_t d = (int64_t)(kp.m - 1) * kp.tau;
+    const bool cross = b != nullptr;
+    const int64_t n = na_points - d, nb = cross ? nb_points - d : n;
+    PlotDesc pd{};
+    pd.a = a;
+    pd.b = cross ? b : a;
+    pd.tail = tail;
+    pd.bits = bits;
+    pd.words = words;
+    pd.nb_points = cross ? nb_points : na_points;
+    pd.n = (int32_t)n;
+    pd.nb = (int32_t)nb;
+    pd.m = kp.m;
+    pd.tau = kp.tau;
+    pd.theiler = kp.theiler;
+    pd.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
+    pd.row_tiles = (int32_t)((n + 63) / 64);
+    pd.col_tiles = (int32_t)((nb + 63) / 64);
+    pd.chunks = (pd.col_tiles + kPlotChunk - 1) / kPlotChunk;
+    pd.cross = cross ? 1 : 0;
+    pd.tail_len = (int32_t)engine_plot_tail_floats(kp);
+    hipLaunchKernelGGL(k_plot_tail, dim3((pd.tail_len + 255) / 256), dim3(256), 0, st, pd);
+    PlotKernel kern = kp.norm == RQA_NORM_L1 ? pick_plot<RQA_NORM_L1>(kp.m)
+                      : kp.norm == RQA_NORM_L2 ? pick_plot<RQA_NORM_L2>(kp.m)
+                                               : pick_plot<RQA_NORM_LINF>(kp.m);
+    const int64_t waves = (int64_t)pd.row_tiles * pd.chunks;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, pd);
     return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
 }
 

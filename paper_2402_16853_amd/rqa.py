@@ -241,6 +241,31 @@ class RQA:
         self._hlen = [max(int(n_rows), int(n_cols)) + 1]
         return self
 
+    def plot(self, series, other=None, words: int | None = None, stream=None):
+        """Recurrence plot of a device series (or the cross recurrence plot of
+        series and ``other``): a device int64 tensor (rows, words), bit b of word
+        c of row i = cell (i, 64c+b).  Enqueued on the stream; the tensor is
+        ready once the stream reaches this point."""
+        import torch
+        s = _device_series(series)
+        d = (self.params.m - 1) * self.params.tau
+        n = s.numel() - d
+        nb = n if other is None else other.numel() - d
+        if n < 1 or nb < 1:
+            raise RQAError(-2, "plot: series too short for the embedding")
+        words = (nb + 63) // 64 if words is None else int(words)
+        out = torch.empty((n, words), dtype=torch.int64, device=s.device)
+        if other is None:
+            rc = lib().rqa_plot(self._h, ctypes.c_void_p(s.data_ptr()), s.numel(),
+                                ctypes.c_void_p(out.data_ptr()), words, _stream_ptr(stream))
+        else:
+            o = _device_series(other)
+            rc = lib().rqa_plot_cross(self._h, ctypes.c_void_p(s.data_ptr()), s.numel(),
+                                      ctypes.c_void_p(o.data_ptr()), o.numel(),
+                                      ctypes.c_void_p(out.data_ptr()), words, _stream_ptr(stream))
+        check(rc, "rqa_plot")
+        return out
+
     def matrix(self, bits, n_cols: int, stream=None) -> RQAResult:
         self.run_matrix(bits, n_cols, stream)
         return self.result()

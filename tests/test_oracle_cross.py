@@ -110,3 +110,32 @@ def test_given_matrix_matches_cross_oracle():
     R = brute.cross_matrix(a, b, 2, 1, 0.2, 1, 0)
     got = oracle.matrix_histograms(brute.pack_rows(R), len(R), len(R[0]), 0)
     assert same(got, oracle.cross_histograms(a, b, 2, 1, 0.2, 1, 0))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_plot_matches_brute_force(seed):
+    rng = np.random.default_rng(300 + seed)
+    m, tau = int(rng.integers(1, 4)), int(rng.integers(1, 3))
+    n = int(rng.integers(1, 80)) + (m - 1) * tau
+    s = rng.random(n).astype(np.float32)
+    p = Params(m=m, tau=tau, eps=float(rng.uniform(0.1, 0.5)), norm=int(rng.integers(1, 4)),
+               theiler=int(rng.choice([0, 1, 3])))
+    got = oracle.plot(s, p)
+    assert np.array_equal(got, brute.pack_rows(brute.matrix(s, m, tau, p.eps, p.norm, p.theiler)))
+    b = rng.random(int(rng.integers(1, 90)) + (m - 1) * tau).astype(np.float32)
+    got = oracle.plot(s, p, b)
+    ref = brute.pack_rows(brute.cross_matrix(s, b, m, tau, p.eps, p.norm, p.theiler))
+    assert np.array_equal(got, ref)
+
+
+def test_plot_histograms_match_line_oracles():
+    """Lines counted on the packed plot equal the auto and cross line oracles."""
+    rng = np.random.default_rng(77)
+    s = (np.cumsum(rng.normal(size=900)) * 0.1).astype(np.float32)
+    b = (np.cumsum(rng.normal(size=700)) * 0.1).astype(np.float32)
+    p = Params(m=3, tau=2, eps=0.2, norm=2, theiler=2)
+    n, nb = 896, 696
+    assert same(oracle.matrix_histograms(oracle.plot(s, p), n, n, 0),
+                oracle.histograms(s, 3, 2, 0.2, 2, 2))
+    assert same(oracle.matrix_histograms(oracle.plot(s, p, b), n, nb, 0),
+                oracle.cross_histograms(s, b, 3, 2, 0.2, 2, 2))
