@@ -16,6 +16,10 @@ Also reported (outside the timed K steps):
   served        a Poisson stream (200 req/s) of mixed jobs through the
                 continuous-batching server: p50/p99 latency and Gcells/s, vs the
                 same jobs run one by one
+  cross / plot / matrix
+                cross recurrence of two Lorenz trajectories (262,144 points each),
+                the packed recurrence plot of 65,536 points, and the RQA of that
+                plot as a given matrix
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
@@ -233,6 +237,81 @@ def bench_batched(args, torch, RQA, workload, windows_plan):
             "speedup_vs_sequential": round(ts / tb, 3)}
 
 
+def bench_full_matrices(args, torch, RQA, workload):
+    """Cross recurrence of two Lorenz trajectories, the recurrence plot of one,
+    and the RQA of that plot as a given matrix (headline embedding and radius)."""
+    n_pts = 262_144
+    a, p = workload("lorenz", seed=args.seed + 1, n=n_pts)
+    b, _ = workload("lorenz", seed=args.seed + 2, n=n_pts)
+    d = (p.m - 1) * p.tau
+    dev = torch.device("cuda:0")
+    da, db = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    comp = RQA.from_params(p)
+    comp.set_profiling(True)
+    out = {}
+    # cross recurrence: every cell of the n_a x n_b matrix is evaluated
+    na, nb = n_pts - d, n_pts - d
+    for _ in range(2):
+        comp.run_cross(da, db)
+        comp.result(histograms=False)
+    tm, tl = [], []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        comp.run_cross(da, db)
+        r = comp.result(histograms=False)
+        tm.append(time.perf_counter() - t0)
+        tl.append(comp.timings()["tiles_ms"])
+    cells = float(na) * nb
+    ms = float(np.median(tm)) * 1e3
+    tile_ms = float(np.median(tl))
+    ops = cells * ops_per_pair(p.m, p.norm)
+    out["cross"] = {"workload": f"lorenz63_x seeds {args.seed + 1},{args.seed + 2} N={n_pts} each, "
+                                f"m={p.m} tau={p.tau} Linf eps={p.eps:.6g}",
+                    "cells": cells, "ms": round(ms, 3), "gcells_per_s": round(cells / ms / 1e6, 3),
+                    "tiles_ms": round(tile_ms, 3),
+                    "valu_frac": round(ops / (tile_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+                    "rr": r.measures["rr"], "det": r.measures["det"]}
+    log(f"[bench] cross: {ms:.2f} ms, tiles {tile_ms:.2f} ms")
+    # recurrence plot of the first 65,536 points, then its RQA as a given matrix
+    n_plot = 65_536
+    n = n_plot - d
+    words = (n + 63) // 64
+    dsp = da[:n_plot].contiguous()
+    bits = comp.plot(dsp)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tp = []
+    for _ in range(3):
+        ev0.record()
+        bits = comp.plot(dsp)
+        ev1.record()
+        torch.cuda.synchronize()
+        tp.append(ev0.elapsed_time(ev1))
+    pms = float(np.median(tp))
+    wbytes = float(n) * words * 8
+    out["plot"] = {"workload": f"recurrence plot of lorenz63_x N={n_plot}, packed {n}x{words} words",
+                   "ms": round(pms, 3), "gcells_per_s": round(float(n) * n / pms / 1e6, 3),
+                   "write_gb_per_s": round(wbytes / pms / 1e6, 3), "bytes_written": wbytes}
+    log(f"[bench] plot: {pms:.3f} ms")
+    for _ in range(2):
+        comp.run_matrix(bits, n)
+        comp.result(histograms=False)
+    tl = []
+    for _ in range(3):
+        comp.run_matrix(bits, n)
+        comp.result(histograms=False)
+        tl.append(comp.timings()["tiles_ms"])
+    mms = float(np.median(tl))
+    out["matrix"] = {"workload": f"given {n}x{n} bit matrix (the plot above)",
+                     "tiles_ms": round(mms, 3), "gcells_per_s": round(float(n) * n / mms / 1e6, 3),
+                     "read_gb_per_s": round(wbytes / mms / 1e6, 3),
+                     "hbm_frac": round(wbytes / mms / 1e6 / 8000.0, 4)}
+    log(f"[bench] matrix: tiles {mms:.3f} ms")
+    comp.close()
+    return out
+
+
 def bench_served(args, torch, RQA, Server, served_requests):
     reqs = served_requests(args.requests, rate_hz=200.0, seed=args.seed)
     dev = torch.device("cuda:0")
@@ -320,7 +399,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--only", default="", help="comma list of extra phases to run after the "
-                    "headline: batched, served, cpu (default: all)")
+                    "headline: batched, served, full, cpu (default: all)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = default)")
     ap.add_argument("--sweep", action="store_true", help="time the tile kernel per waves setting")
     ap.add_argument("--probe-valu", action="store_true",
@@ -365,6 +444,8 @@ def main():
         extra["batched"] = bench_batched(args, torch, RQA, workload, windows_plan)
     if want("served", args.no_served):
         extra["served"] = bench_served(args, torch, RQA, Server, served_requests)
+    if want("full", False):
+        extra.update(bench_full_matrices(args, torch, RQA, workload))
     cpu = None
     if want("cpu", args.no_cpu):
         cpu = bench_cpu_baseline(args, hl)
