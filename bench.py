@@ -45,6 +45,10 @@ METRIC = "recurrence cells/s (Gcells/s) full RQA @N=1M, 1 GPU; batched p50/p99 l
 # x 2.  The predicate's operations (subtract, max, compare) are one operation per
 # lane each, so their peak is 256 x 2.4e9 x 128 = 78.6 T ops/s.
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
+# Sustained rate of the predicate's own instruction stream (L-infinity, m=3:
+# 6 VALU per column, 1.25 wave-instructions per clock per CU), measured with
+# --probe-valu on the MI355X: the practical ceiling of the tile kernel.
+PREDICATE_CEILING_TOPS = 48.6
 TILES_SRC = os.path.join(REPO, "paper_2402_16853_amd", "csrc", "rqa_tiles.hip")
 PMC_SUMMARY = os.path.join(REPO, "profiles", "k_tiles_lorenz_N1048576_pmc.md")
 
@@ -160,6 +164,10 @@ def bench_headline(args, torch, RQA, workload):
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
             "traffic": measured_traffic(),
+            "frac_vs_64_lanes": round(achieved / (VALU_PEAK_TOPS / 2), 4),
+            "predicate_ceiling": {"tops": PREDICATE_CEILING_TOPS,
+                                  "frac": round(achieved / PREDICATE_CEILING_TOPS, 4),
+                                  "source": "bench.py --probe-valu (libcalib.so)"},
             "kernel": "k_tiles<Linf,m=3>", "kernel_ms": round(tile_ms, 3),
             "ops_per_launch": ops,
             "stitch_ms": round(float(np.mean(stitch)), 3),
