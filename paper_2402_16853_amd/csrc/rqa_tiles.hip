@@ -65,6 +65,7 @@ constexpr int kMaxM = 6;       // embedding dimensions held in registers
 constexpr int kRing = 4;       // carry slots per pair of consecutive waves (tiles in flight)
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls (~28 ms) before a neighbour wait gives up
 constexpr int kStitchThreads = 256;
+constexpr int kStitchBatch = 8;   // strips whose summaries a stitch thread loads at once
 constexpr int kStatThreads = 256;
 constexpr int kStatMaxBlocks = 64;
 
@@ -344,8 +345,10 @@ __device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__r
 
 // Recurrence bits of one 64x64 tile for this lane's row: bit b <-> column
 // jbase + b.  `cols` points at the coordinate of column jbase (uniform).  The 64
-// columns are taken in four chunks of 16 (highest first), each fully unrolled,
-// so that at most 16*m column coordinates are live in SGPRs.
+// columns are taken in eight chunks of 8 (highest first), each fully unrolled,
+// so that at most 8*m column coordinates are live in SGPRs (chunks of 16 left
+// too few SGPRs for the rest of the kernel, which then spilled into VGPR lanes;
+// measured 10% slower).
 template <int NORM, int M>
 __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
                                           const float *__restrict__ rowp, int m, float thr,
@@ -354,15 +357,15 @@ __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
     for (int half = 1; half >= 0; --half) {
         uint32_t acc = 0;
 #pragma unroll 1
-        for (int sub = 1; sub >= 0; --sub) {
-            const int b0 = half * 32 + sub * 16;
+        for (int sub = 3; sub >= 0; --sub) {
+            const int b0 = half * 32 + sub * 8;
             ConstF cb = cols + b0;
             if (M > 0) {
 #pragma unroll
-                for (int b = 15; b >= 0; --b)
+                for (int b = 7; b >= 0; --b)
                     acc = __builtin_amdgcn_alignbit(acc, nonrec_sign<NORM, M>(cb + b, tau, xr, thr), 31);
             } else {
-                for (int b = 15; b >= 0; --b)
+                for (int b = 7; b >= 0; --b)
                     acc = __builtin_amdgcn_alignbit(
                         acc, nonrec_sign_dyn<NORM>(cb + b, rowp, m, tau, thr), 31);
             }
@@ -473,7 +476,7 @@ __device__ void flush_bins(const StripLds &L, const JobDesc &j) {
 // kModeMatrix: a full n x nb matrix that is not symmetric (every diagonal and
 // every column walked once; no horizontal runs).
 template <int NORM, int M, int MODE>
-__device__ void process_strip(const JobDesc j, int strip, StripLds &L) {
+__device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
     static_assert(kMaxWaves <= 8, "LDS budget assumes at most 8 waves per workgroup");
     constexpr bool FULL = MODE != kModeAuto;
     constexpr int kDW = FULL ? 1 : 2;   // lines per diagonal run found
@@ -808,7 +811,9 @@ k_tiles(const JobDesc *__restrict__ jobs, const GroupDesc *__restrict__ groups, 
             const int mid = (lo + hi + 1) >> 1;
             if (jobs[mid].strip_base <= item) lo = mid; else hi = mid - 1;
         }
-        const JobDesc j = jobs[lo];
+        // By reference: fields are re-read with scalar loads where needed
+        // instead of occupying SGPRs for the whole strip.
+        const JobDesc &j = jobs[lo];
         process_strip<NORM, M, MODE>(j, item - j.strip_base, L);
         __syncthreads();
         flush_bins(L, j);
@@ -843,19 +848,32 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
     if (line < nb) {
         const int col = (int)line;
         uint32_t oc = 0, ol = 0;
-        for (int s = 0; s < S; ++s) {
-            const uint32_t Ls = s < S - 1 ? (uint32_t)H : (uint32_t)(n - s * H);
-            const int64_t idx = (int64_t)s * nb + col;
-            const uint32_t f = j.vfirst[idx], l = j.vlast[idx];
-            const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
-            if (fl == Ls) {   // the segment is one run
-                if (ol && oc == fc) ol += Ls;
-                else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
-            } else {
-                if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
-                else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
-                oc = l >> 15;
-                ol = l & 0x7FFFu;
+        for (int s0 = 0; s0 < S; s0 += kStitchBatch) {
+            uint32_t fv[kStitchBatch], lv[kStitchBatch];
+#pragma unroll
+            for (int u = 0; u < kStitchBatch; ++u) {
+                const int64_t idx = (int64_t)(s0 + u) * nb + col;
+                if (s0 + u < S) {
+                    fv[u] = j.vfirst[idx];
+                    lv[u] = j.vlast[idx];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStitchBatch; ++u) {
+                const int s = s0 + u;
+                if (s >= S) break;
+                const uint32_t Ls = s < S - 1 ? (uint32_t)H : (uint32_t)(n - s * H);
+                const uint32_t f = fv[u], l = lv[u];
+                const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
+                if (fl == Ls) {   // the segment is one run
+                    if (ol && oc == fc) ol += Ls;
+                    else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
+                } else {
+                    if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
+                    else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
+                    oc = l >> 15;
+                    ol = l & 0x7FFFu;
+                }
             }
         }
         emit_line(L, j, oc, ol);
@@ -902,19 +920,35 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
         uint32_t oc = 0, ol = 0;   // open run after folding column `col` of U
         if (col >= wp) {
             const int s_last = (col - wp) / H;
-            for (int s = 0; s <= s_last; ++s) {
-                const uint32_t Ls = s < s_last ? (uint32_t)H : (uint32_t)(col - wp - s * H + 1);
-                const int64_t idx = strip_offset(s, n, wp, H) + (col - s * H - wp);
-                const uint32_t f = j.vfirst[idx], l = j.vlast[idx];
-                const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
-                if (fl == Ls) {   // the segment is one run
-                    if (ol && oc == fc) ol += Ls;
-                    else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
-                } else {
-                    if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
-                    else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
-                    oc = l >> 15;
-                    ol = l & 0x7FFFu;
+            // The summaries of kStitchBatch strips are loaded before any is
+            // folded, so a thread has that many loads in flight.
+            for (int s0 = 0; s0 <= s_last; s0 += kStitchBatch) {
+                uint32_t fv[kStitchBatch], lv[kStitchBatch];
+#pragma unroll
+                for (int u = 0; u < kStitchBatch; ++u) {
+                    const int s = s0 + u;
+                    if (s <= s_last) {
+                        const int64_t idx = strip_offset(s, n, wp, H) + (col - s * H - wp);
+                        fv[u] = j.vfirst[idx];
+                        lv[u] = j.vlast[idx];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kStitchBatch; ++u) {
+                    const int s = s0 + u;
+                    if (s > s_last) break;
+                    const uint32_t Ls = s < s_last ? (uint32_t)H : (uint32_t)(col - wp - s * H + 1);
+                    const uint32_t f = fv[u], l = lv[u];
+                    const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
+                    if (fl == Ls) {   // the segment is one run
+                        if (ol && oc == fc) ol += Ls;
+                        else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
+                    } else {
+                        if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
+                        else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
+                        oc = l >> 15;
+                        ol = l & 0x7FFFu;
+                    }
                 }
             }
         }
@@ -943,12 +977,26 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
         if (k >= wp) {
             const int s_last = (n - 1 - k) / H;
             uint32_t open = 0;
-            for (int s = 0; s <= s_last; ++s) {
-                const int64_t idx = strip_offset(s, n, wp, H) + (k - wp);
-                const uint32_t fb = j.dfirst[idx];
-                if (s < s_last && fb == (uint32_t)H) { open += H; continue; }
-                if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
-                open = s < s_last ? (uint32_t)j.dlast[idx] : 0u;
+            for (int s0 = 0; s0 <= s_last; s0 += kStitchBatch) {
+                uint32_t fv[kStitchBatch], lv[kStitchBatch];
+#pragma unroll
+                for (int u = 0; u < kStitchBatch; ++u) {
+                    const int s = s0 + u;
+                    if (s <= s_last) {
+                        const int64_t idx = strip_offset(s, n, wp, H) + (k - wp);
+                        fv[u] = j.dfirst[idx];
+                        lv[u] = j.dlast[idx];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kStitchBatch; ++u) {
+                    const int s = s0 + u;
+                    if (s > s_last) break;
+                    const uint32_t fb = fv[u];
+                    if (s < s_last && fb == (uint32_t)H) { open += H; continue; }
+                    if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
+                    open = s < s_last ? lv[u] : 0u;
+                }
             }
         } else if (k == 0 && j.theiler == 0) {
             // main diagonal: every cell (i,i) is recurrent (distance 0 <= eps)
