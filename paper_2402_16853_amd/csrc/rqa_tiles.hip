@@ -257,31 +257,48 @@ __device__ __forceinline__ void finish_run(const LineCtx &lc, uint32_t c, uint32
     }
 }
 
+// A run that starts and ends inside one window: 1 <= len <= 63, never the
+// first run of a segment, below every LDS bin cap and every histogram length.
+template <int KIND, int DW>
+__device__ __forceinline__ void emit_inner(const LineCtx &lc, uint32_t c, uint32_t len) {
+    if (KIND == kDiag) {
+        if (c) atomicAdd(lc.bins.d + len, (uint32_t)DW);
+    } else {
+        atomicAdd((c ? lc.bins.v : lc.bins.w) + len, 1u);
+    }
+}
+
+// Index of the lowest set bit of a non-zero 64-bit word.
+__device__ __forceinline__ uint32_t low_bit(uint64_t t) { return (uint32_t)__builtin_ctzll(t); }
+
 // Advance `st` over the bits [lo, hi) of x (win = mask of those bits),
-// finishing every run that ends there.  The common case -- no colour change in
-// the window -- costs a few VALU operations.
+// finishing every run that ends there.  The colour changes are the set bits
+// of x ^ (x shifted by one, with the open run's colour entering at lo).  The
+// first change ends the open run (which may be a segment's first run or carry a
+// long length); every later run lies inside the window.
 template <int KIND, int DW = 2>
 __device__ __forceinline__ void run_segment(uint64_t x, uint64_t win, uint32_t lo, uint32_t hi,
                                             Run &st, const LineCtx &lc) {
-    uint64_t diff = (st.color ? ~x : x) & win;
-    if (diff == 0) {
+    if (lo >= hi) return;
+    const uint64_t prev = ((x << 1) & ~(1ull << lo)) | ((uint64_t)st.color << lo);
+    uint64_t t = (x ^ prev) & win;
+    if (t == 0) {
         st.len += hi - lo;
         return;
     }
-    uint32_t pos = lo;
-    while (true) {
-        const uint32_t p = (uint32_t)__builtin_ctzll(diff);
-        finish_run<KIND, DW>(lc, st.color, st.len + (p - pos), st.first);
-        st.first = 0;
-        st.color ^= 1u;
-        st.len = 0;
-        pos = p;
-        diff = (st.color ? ~x : x) & win & (~0ull << pos);
-        if (diff == 0) {
-            st.len = hi - pos;
-            return;
-        }
+    uint32_t p = low_bit(t);
+    finish_run<KIND, DW>(lc, st.color, st.len + (p - lo), st.first);
+    uint32_t c = st.color ^ 1u;
+    uint32_t sp = p;
+    t &= t - 1ull;
+    while (t) {
+        p = low_bit(t);
+        emit_inner<KIND, DW>(lc, c, p - sp);
+        c ^= 1u;
+        sp = p;
+        t &= t - 1ull;
     }
+    st = Run{c, hi - sp, 0u};
 }
 
 // Series pointer in the constant address space: loads through it with a
