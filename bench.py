@@ -20,6 +20,8 @@ Also reported (outside the timed K steps):
                 cross recurrence of two Lorenz trajectories (262,144 points each),
                 the packed recurrence plot of 65,536 points, and the RQA of that
                 plot as a given matrix
+  paper_e2      the paper's own runtime workload (1,000,001-point sine), timed as
+                a full RQA and set beside the paper's totals (Tab. 4)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
@@ -53,26 +55,44 @@ TILES_SRC = os.path.join(REPO, "paper_2402_16853_amd", "csrc", "rqa_tiles.hip")
 PMC_SUMMARY = os.path.join(REPO, "profiles", "k_tiles_lorenz_N1048576_pmc.md")
 
 
-def measured_traffic():
-    """HBM bytes per k_tiles launch from the committed FETCH_SIZE / WRITE_SIZE
-    summary, or None when the kernel source has changed since it was taken."""
+def profile_fields():
+    """Figures of the committed k_tiles counter summary, or {} when the kernel
+    source has changed since the counters were taken."""
     import hashlib
     try:
         text = open(PMC_SUMMARY).read()
     except OSError:
-        return None
+        return {}
     fields = {}
     for line in text.splitlines():
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
     sha = hashlib.sha256(open(TILES_SRC, "rb").read()).hexdigest()
-    if fields.get("kernel source sha256") != sha:
-        return None
+    return fields if fields.get("kernel source sha256") == sha else {}
+
+
+def measured_traffic():
+    """HBM bytes per k_tiles launch from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel source has changed since it was taken."""
     try:
-        return int(fields["HBM bytes per launch"].replace(",", ""))
+        return int(profile_fields()["HBM bytes per launch"])
     except (KeyError, ValueError):
         return None
+
+
+def measured_lds(kernel_ms):
+    """LDS throughput of k_tiles: the committed per-launch LDS bytes over this
+    run's kernel time, against the probed LDS read peak (None if stale)."""
+    f = profile_fields()
+    try:
+        nbytes = int(f["LDS bytes per launch"])
+        peak = float(f["LDS peak TB/s"])
+    except (KeyError, ValueError):
+        return None
+    tbps = nbytes / (kernel_ms * 1e-3) / 1e12
+    return {"achieved": round(tbps, 3), "peak": peak, "unit": "TB/s", "frac": round(tbps / peak, 4),
+            "bytes_per_launch": nbytes}
 
 
 def log(*a):
@@ -164,6 +184,7 @@ def bench_headline(args, torch, RQA, workload):
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
             "traffic": measured_traffic(),
+            "lds": measured_lds(tile_ms),
             "frac_vs_64_lanes": round(achieved / (VALU_PEAK_TOPS / 2), 4),
             "predicate_ceiling": {"tops": PREDICATE_CEILING_TOPS,
                                   "frac": round(achieved / PREDICATE_CEILING_TOPS, 4),
@@ -320,6 +341,39 @@ def bench_full_matrices(args, torch, RQA, workload):
     return out
 
 
+def bench_paper_e2(args, torch, RQA, workload):
+    """The paper's runtime workload (Sect. 8.2): sin(linspace(0, 1000 pi, 1000001)),
+    m=2, tau=2, radius 1.0 (Euclidean), minimum lengths 2, with and without the
+    line of identity; full RQA (histograms and measures to the host), compared
+    with the paper's totals on its stated hardware (Tab. 4)."""
+    s, p = workload("sine")
+    dev = torch.device("cuda:0")
+    ds = torch.from_numpy(s).to(dev)
+    out = {"workload": "sin(linspace(0, 1000 pi, 1000001)), m=2, tau=2, L2, eps=1.0, min lengths 2",
+           "paper_4gpu_s": 68.94, "paper_1gpu_s": 204.81,
+           "paper_hardware": "GTX 690 processors (4 GPUs / 1 GPU), OpenCL, Tab. 4",
+           "paper_crp_s": 28480.09}
+    for w in (1, 0):
+        q = type(p)(m=p.m, tau=p.tau, eps=p.eps, norm=p.norm, lmin=2, vmin=2, wmin=2, theiler=w)
+        comp = RQA.from_params(q)
+        comp.run(ds)
+        comp.result(histograms=True)
+        t = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            comp.run(ds)
+            r = comp.result(histograms=True)
+            t.append(time.perf_counter() - t0)
+        comp.close()
+        sec = float(np.median(t))
+        out[f"theiler{w}"] = {"s": round(sec, 4), "rr": r.measures["rr"], "det": r.measures["det"],
+                              "speedup_vs_paper_1gpu": round(204.81 / sec, 1),
+                              "speedup_vs_paper_4gpu": round(68.94 / sec, 1)}
+        log(f"[bench] paper E2 sine, Theiler {w}: {sec * 1e3:.1f} ms")
+    return out
+
+
 def bench_served(args, torch, RQA, Server, served_requests):
     reqs = served_requests(args.requests, rate_hz=200.0, seed=args.seed)
     dev = torch.device("cuda:0")
@@ -394,6 +448,26 @@ def probe_valu():
                           "predicate_tops": round(ops, 3)}), flush=True)
 
 
+def probe_lds():
+    """LDS read bandwidth (conflict-free 16-byte reads), TB/s and bytes per clock
+    per CU at 2.4 GHz."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(REPO, "paper_2402_16853_amd", "libcalib.so"))
+    lib.calib_lds.restype = ctypes.c_int
+    lib.calib_lds.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_double)]
+    iters = 20000
+    for blocks, threads in ((256, 1024), (512, 1024), (512, 512), (1024, 256)):
+        ms = ctypes.c_double()
+        rc = lib.calib_lds(blocks, threads, iters, ctypes.byref(ms))
+        nbytes = float(blocks) * threads * iters * 16
+        tbps = nbytes / (ms.value * 1e-3) / 1e12
+        print(json.dumps({"probe": "lds", "blocks": blocks, "threads": threads, "rc": rc,
+                          "ms": round(ms.value, 3), "tb_per_s": round(tbps, 3),
+                          "bytes_per_clk_per_cu_at_2.4GHz": round(tbps * 1e12 / 256 / 2.4e9, 1)}),
+              flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,12 +481,14 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--only", default="", help="comma list of extra phases to run after the "
-                    "headline: batched, served, full, cpu (default: all)")
+                    "headline: batched, served, full, e2, cpu (default: all)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = default)")
     ap.add_argument("--sweep", action="store_true", help="time the tile kernel per waves setting")
     ap.add_argument("--probe-valu", action="store_true",
                     help="only measure the issue rate of the predicate's VALU instruction "
                          "stream (libcalib.so) and exit")
+    ap.add_argument("--probe-lds", action="store_true",
+                    help="only measure the LDS read bandwidth (libcalib.so) and exit")
     ap.add_argument("--probe-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -428,6 +504,9 @@ def main():
         sys.exit(1)
     if args.probe_valu:
         probe_valu()
+        return
+    if args.probe_lds:
+        probe_lds()
         return
     if args.probe_copy:
         n = args.probe_copy * (1 << 20) // 4
@@ -454,6 +533,8 @@ def main():
         extra["served"] = bench_served(args, torch, RQA, Server, served_requests)
     if want("full", False):
         extra.update(bench_full_matrices(args, torch, RQA, workload))
+    if want("e2", False):
+        extra["paper_e2"] = bench_paper_e2(args, torch, RQA, workload)
     cpu = None
     if want("cpu", args.no_cpu):
         cpu = bench_cpu_baseline(args, hl)

@@ -1,9 +1,10 @@
-// Calibration kernel for the roofline of the RQA tile kernel: the sustained
-// issue rate of exactly the predicate's instruction stream (L-infinity, m = 3:
+// Calibration kernels for the roofline of the RQA tile kernel.  (1) The
+// sustained issue rate of exactly the predicate's instruction stream (L-infinity, m = 3:
 // three v_sub_f32 with a scalar operand, v_max3_f32 with |x| modifiers, one
 // v_sub_f32 and one v_alignbit_b32 per column; column coordinates from
-// s_load_dwordx16), with nothing else in the loop.  Built into libcalib.so and
-// used only by bench.py --probe-valu.
+// s_load_dwordx16), with nothing else in the loop.  (2) The LDS read
+// bandwidth with conflict-free 16-byte reads.  Built into libcalib.so and used
+// only by bench.py --probe-valu / --probe-lds.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -42,9 +43,48 @@ __global__ void __launch_bounds__(512) k_predicate_only(const float *__restrict_
     if (sink == 0x9E3779B9u) out[lane] = sink;   // keeps the work observable
 }
 
+// LDS read rate: each lane reads 16 bytes per step (ds_read_b128) at addresses
+// that cover all banks without conflicts; 64 KB of LDS per workgroup.
+__global__ void __launch_bounds__(1024) k_lds_read(int iters, uint32_t *out) {
+    __shared__ uint4 buf[4096];
+    for (int t = threadIdx.x; t < 4096; t += blockDim.x)
+        buf[t] = make_uint4(t, t * 3u, t * 5u, t * 7u);
+    __syncthreads();
+    uint32_t acc = 0;
+    int idx = threadIdx.x & 4095;
+    for (int it = 0; it < iters; ++it) {
+        const uint4 v = buf[idx];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+        idx = (idx + 64) & 4095;
+    }
+    if (acc == 0x9E3779B9u) out[threadIdx.x] = acc;   // keeps the work observable
+}
+
 }  // namespace
 
 extern "C" {
+
+// LDS read bandwidth probe: `blocks` x `threads` lanes each read 16 bytes per
+// step for `iters` steps; elapsed milliseconds returned in *ms.
+int calib_lds(int blocks, int threads, int iters, double *ms) {
+    uint32_t *out = nullptr;
+    if (hipMalloc(&out, 1024 * sizeof(uint32_t)) != hipSuccess) return -1;
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipLaunchKernelGGL(k_lds_read, dim3(blocks), dim3(threads), 0, 0, 16, out);
+    hipEventRecord(a, 0);
+    hipLaunchKernelGGL(k_lds_read, dim3(blocks), dim3(threads), 0, 0, iters, out);
+    hipEventRecord(b, 0);
+    hipEventSynchronize(b);
+    float t = 0.f;
+    hipEventElapsedTime(&t, a, b);
+    *ms = t;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    hipFree(out);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
 
 // Launch `blocks` workgroups of `threads` (multiple of 64) for `iters` chunks of
 // 16 columns each and return the elapsed milliseconds (hipEvents).  Each chunk
