@@ -1,7 +1,7 @@
 // Calibration kernels for the roofline of the RQA tile kernel.  (1) The
 // sustained issue rate of exactly the predicate's instruction stream (L-infinity, m = 3:
 // three v_sub_f32 with a scalar operand, v_max3_f32 with |x| modifiers, one
-// v_sub_f32 and one v_alignbit_b32 per column; column coordinates from
+// v_sub_f32 from the threshold in a VGPR and one v_alignbit_b32 per column; column coordinates from
 // s_load_dwordx16), with nothing else in the loop.  (2) The LDS read
 // bandwidth with conflict-free 16-byte reads.  Built into libcalib.so and used
 // only by bench.py --probe-valu / --probe-lds.
@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(512) k_predicate_only(const float *__restrict_
     const float x0 = s[lane & 1023], x1 = s[(lane + kTau) & 1023], x2 = s[(lane + 2 * kTau) & 1023];
     const ConstF cs = (ConstF)(s);
     uint32_t acc = 0, sink = 0;
+    asm volatile("" : "+v"(thr));   // threshold in a VGPR, as in the tile kernel
     int base = __builtin_amdgcn_readfirstlane(blockIdx.x * 16) & 2047;
     for (int it = 0; it < iters; ++it) {
         acc = tile16(cs + base, x0, x1, x2, thr, acc);

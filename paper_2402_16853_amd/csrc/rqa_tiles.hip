@@ -201,6 +201,22 @@ __device__ __forceinline__ Run unpack_run(uint32_t v) {
     return Run{(v >> 16) & 1u, v & 0xFFFFu, (v >> 17) & 1u};
 }
 
+// Global-memory access through address-space-1 pointers.  The kernels reach
+// HBM through pointers held in the job descriptor, which the compiler cannot
+// prove global; it would emit flat instructions, and every flat access also
+// counts against the LDS/scalar wait counter, so a later wait for a scalar load
+// would also wait for outstanding histogram atomics and summary stores.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *glb(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+__device__ __forceinline__ void g_add(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_add(glb(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_or(int *p, int v) {
+    __hip_atomic_fetch_or(glb(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct Bins {
     uint32_t *d, *v, *w;
 };
@@ -213,9 +229,9 @@ __device__ __forceinline__ void emit(uint32_t *bins, int cap, unsigned long long
     if (len < (uint32_t)cap && len <= n)
         atomicAdd(bins + len, wt);
     else if (len <= n)
-        atomicAdd(glob + len, (unsigned long long)wt);
+        g_add(glob + len, (unsigned long long)wt);
     else
-        atomicOr(flag, 2);
+        g_or(flag, 2);
 }
 
 enum LineKind { kHoriz = 0, kVert = 1, kDiag = 2 };
@@ -236,20 +252,20 @@ __device__ __forceinline__ void finish_run(const LineCtx &lc, uint32_t c, uint32
     const JobDesc &j = *lc.jd;
     if (KIND == kDiag) {
         if (first) {
-            if (lc.sum_ok) j.dfirst[lc.sum_idx] = (uint16_t)(c ? len : 0u);
+            if (lc.sum_ok) *glb(j.dfirst + lc.sum_idx) = (uint16_t)(c ? len : 0u);
         } else if (c) {
             emit(lc.bins.d, kCapD, j.hd, len, (uint32_t)DW, (uint32_t)j.hmax, j.flag);
         }
     } else if (KIND == kVert) {
         if (first)
-            j.vfirst[lc.sum_idx] = (uint16_t)(len | (c << 15));
+            *glb(j.vfirst + lc.sum_idx) = (uint16_t)(len | (c << 15));
         else if (c)
             emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
         else
             emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
     } else {
         if (first)
-            j.lead[lc.row] = len | (c << 31);
+            *glb(j.lead + lc.row) = len | (c << 31);
         else if (c)
             emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
         else
@@ -340,8 +356,9 @@ __device__ __forceinline__ uint32_t nonrec_sign(ConstF col, int tau, const float
 
 // Generic embedding dimension: row coordinates read from memory.
 template <int NORM>
-__device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__restrict__ row,
+__device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__restrict__ rowp,
                                                     int m, int tau, float thr) {
+    const auto row = glb(rowp);
     float a;
     if (NORM == RQA_NORM_L1) {
         a = fabsf(col[0] - row[0]);
@@ -368,8 +385,15 @@ __device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__r
 // measured 10% slower).
 template <int NORM, int M>
 __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
-                                          const float *__restrict__ rowp, int m, float thr,
+                                          const float *__restrict__ rowp, int m, float thr_s,
                                           uint32_t &lo, uint32_t &hi) {
+    // The threshold is uniform, but as a scalar operand it would make the last
+    // subtraction read an SGPR too; VALU instructions with only VGPR operands
+    // issue faster on gfx950 (measured: the six-instruction L-infinity column
+    // sustains ~1.5 instead of ~1.2 wave-instructions per clock per CU).  The
+    // empty asm pins the copy in a VGPR.
+    float thr = thr_s;
+    asm volatile("" : "+v"(thr));
 #pragma unroll 1
     for (int half = 1; half >= 0; --half) {
         uint32_t acc = 0;
@@ -476,14 +500,14 @@ __device__ void flush_bins(const StripLds &L, const JobDesc &j) {
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
         if (t < kCapD) {
             const uint32_t v = L.bd[t];
-            if (v) { if (t < hl) atomicAdd(j.hd + t, (unsigned long long)v); L.bd[t] = 0; }
+            if (v) { if (t < hl) g_add(j.hd + t, (unsigned long long)v); L.bd[t] = 0; }
         }
         if (t < kCapV) {
             const uint32_t v = L.bv[t];
-            if (v) { if (t < hl) atomicAdd(j.hv + t, (unsigned long long)v); L.bv[t] = 0; }
+            if (v) { if (t < hl) g_add(j.hv + t, (unsigned long long)v); L.bv[t] = 0; }
         }
         const uint32_t v = L.bw[t];
-        if (v) { if (t < hl) atomicAdd(j.hw + t, (unsigned long long)v); L.bw[t] = 0; }
+        if (v) { if (t < hl) g_add(j.hw + t, (unsigned long long)v); L.bw[t] = 0; }
     }
 }
 
@@ -527,7 +551,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
     float xr[M > 0 ? M : 1] = {};
     if constexpr (MODE != kModeMatrix) {
 #pragma unroll
-        for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? rowp[(int64_t)k * tau] : 0.0f;
+        for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? glb(rowp)[(int64_t)k * tau] : 0.0f;
     }
 
     Bins bins{L.bd, L.bv, L.bw};
@@ -631,8 +655,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     }
                     if (wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
-                        j.vlast[sidx] = pk;
-                        if (st.first) j.vfirst[sidx] = pk;
+                        *glb(j.vlast + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;
                     } else {
                         L.vs(slot, wave, lane) = pack_run(st);
                     }
@@ -644,7 +668,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     const int klo = kup - 64;
                     Run up;
                     if (wave == 0) {
-                        if (!FULL || dok(kup)) j.dfirst[dbase + kup] = 0;   // white first cell
+                        if (!FULL || dok(kup)) *glb(j.dfirst + dbase + kup) = 0;   // white first cell
                         up = Run{0u, 0u, 0u};
                     } else {
                         up = unpack_run(L.ds(slot, wave - 1, lane));
@@ -666,8 +690,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                         L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (!FULL || dok(klo)) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        j.dlast[dbase + klo] = b;
-                        if (lw.first) j.dfirst[dbase + klo] = b;
+                        *glb(j.dlast + dbase + klo) = b;
+                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
                     }
                     left = up;
                 }
@@ -708,8 +732,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     run_segment<kVert>(Y, vwin, 0u, vhi, st, lc);
                     if (e <= 63 || wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
-                        j.vlast[sidx] = pk;
-                        if (st.first) j.vfirst[sidx] = pk;
+                        *glb(j.vlast + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;
                     } else {
                         L.vs(slot, wave, lane) = pack_run(st);
                     }
@@ -739,7 +763,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     // does not matter).
                     up = Run{(uint32_t)(D & 1ull), 0u, 1u};
                     if (!up.color) {
-                        if (dok(kup)) j.dfirst[dbase + kup] = 0;
+                        if (dok(kup)) *glb(j.dfirst + dbase + kup) = 0;
                         up.first = 0;
                     }
                 } else if (jbase + q > nb - 1) {
@@ -768,8 +792,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                         L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (ok) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        j.dlast[dbase + klo] = b;
-                        if (lw.first) j.dfirst[dbase + klo] = b;
+                        *glb(j.dlast + dbase + klo) = b;
+                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
                     }
                 }
                 left = up;
@@ -778,7 +802,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
         if (wave > 0) publish_counter(&L.cons[wave - 1], t + 1);
         if (wave < nw - 1) publish_counter(&L.prod[wave], t + 1);
     }
-    if (!sync_ok) atomicOr(j.flag, 8);   // a neighbour wait gave up: result invalid
+    if (!sync_ok) g_or(j.flag, 8);   // a neighbour wait gave up: result invalid
 
     if (wave_has_u) {
         // Rows end at column n-1: their last run is complete.
@@ -871,8 +895,8 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
             for (int u = 0; u < kStitchBatch; ++u) {
                 const int64_t idx = (int64_t)(s0 + u) * nb + col;
                 if (s0 + u < S) {
-                    fv[u] = j.vfirst[idx];
-                    lv[u] = j.vlast[idx];
+                    fv[u] = *glb(j.vfirst + idx);
+                    lv[u] = *glb(j.vlast + idx);
                 }
             }
 #pragma unroll
@@ -903,10 +927,10 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
         for (int s = sf; s <= sl; ++s) {
             const int64_t idx = (int64_t)s * (nb + H - 1) + (k + s * H + H - 1);
             const bool top = s > sf || r0 == s * H;
-            const uint32_t fb = top ? (uint32_t)j.dfirst[idx] : 0u;
+            const uint32_t fb = top ? (uint32_t)*glb(j.dfirst + idx) : 0u;
             if (s < sl && top && fb == (uint32_t)H) { open += H; continue; }
             if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 1u, (uint32_t)j.hmax, j.flag);
-            open = s < sl ? (uint32_t)j.dlast[idx] : 0u;
+            open = s < sl ? (uint32_t)*glb(j.dlast + idx) : 0u;
         }
     }
 }
@@ -946,8 +970,8 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
                     const int s = s0 + u;
                     if (s <= s_last) {
                         const int64_t idx = strip_offset(s, n, wp, H) + (col - s * H - wp);
-                        fv[u] = j.vfirst[idx];
-                        lv[u] = j.vlast[idx];
+                        fv[u] = *glb(j.vfirst + idx);
+                        lv[u] = *glb(j.vlast + idx);
                     }
                 }
 #pragma unroll
@@ -982,7 +1006,7 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
         if (ol && oc == mc) ol += ml;
         else { emit_line(L, j, oc, ol); oc = mc; ol = ml; }
         if (col + wp <= n - 1) {
-            const uint32_t ld = j.lead[col];
+            const uint32_t ld = *glb(j.lead + col);
             const uint32_t hc = ld >> 31, hl = ld & 0x7FFFFFFFu;
             if (oc == hc) ol += hl;
             else { emit_line(L, j, oc, ol); oc = hc; ol = hl; }
@@ -1001,8 +1025,8 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
                     const int s = s0 + u;
                     if (s <= s_last) {
                         const int64_t idx = strip_offset(s, n, wp, H) + (k - wp);
-                        fv[u] = j.dfirst[idx];
-                        lv[u] = j.dlast[idx];
+                        fv[u] = *glb(j.dfirst + idx);
+                        lv[u] = *glb(j.dlast + idx);
                     }
                 }
 #pragma unroll
@@ -1023,9 +1047,9 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
     __syncthreads();
     const int hl = n + 1;
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
-        if (t < kCapD && L.bd[t] && t < hl) atomicAdd(j.hd + t, (unsigned long long)L.bd[t]);
-        if (t < kCapV && L.bv[t] && t < hl) atomicAdd(j.hv + t, (unsigned long long)L.bv[t]);
-        if (L.bw[t] && t < hl) atomicAdd(j.hw + t, (unsigned long long)L.bw[t]);
+        if (t < kCapD && L.bd[t] && t < hl) g_add(j.hd + t, (unsigned long long)L.bd[t]);
+        if (t < kCapV && L.bv[t] && t < hl) g_add(j.hv + t, (unsigned long long)L.bv[t]);
+        if (L.bw[t] && t < hl) g_add(j.hw + t, (unsigned long long)L.bw[t]);
     }
 }
 
@@ -1171,7 +1195,7 @@ __global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
     const float *rowp = d.a + irow;
     float xr[M > 0 ? M : 1];
 #pragma unroll
-    for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? rowp[(int64_t)k * d.tau] : 0.0f;
+    for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? glb(rowp)[(int64_t)k * d.tau] : 0.0f;
     int cbeg = q * kPlotChunk;
     const int cend = cbeg + kPlotChunk < d.col_tiles ? cbeg + kPlotChunk : d.col_tiles;
     if (!d.cross && cbeg < r) cbeg = r;
