@@ -48,9 +48,10 @@ METRIC = "recurrence cells/s (Gcells/s) full RQA @N=1M, 1 GPU; batched p50/p99 l
 # lane each, so their peak is 256 x 2.4e9 x 128 = 78.6 T ops/s.
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # Sustained rate of the predicate's own instruction stream (L-infinity, m=3:
-# 6 VALU per column, 1.25 wave-instructions per clock per CU), measured with
-# --probe-valu on the MI355X: the practical ceiling of the tile kernel.
-PREDICATE_CEILING_TOPS = 48.6
+# 6 VALU per column, threshold in a VGPR, 1.42 wave-instructions per clock per
+# CU at eight waves per SIMD), measured with --probe-valu on the MI355X: the
+# practical ceiling of the tile kernel.
+PREDICATE_CEILING_TOPS = 55.4
 TILES_SRC = os.path.join(REPO, "paper_2402_16853_amd", "csrc", "rqa_tiles.hip")
 PMC_SUMMARY = os.path.join(REPO, "profiles", "k_tiles_lorenz_N1048576_pmc.md")
 
