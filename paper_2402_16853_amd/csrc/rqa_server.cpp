@@ -4,10 +4,19 @@
 // * The server owns one device pool of `budget` bytes, carved up by a
 //   first-fit allocator; a job is admitted (FIFO) when its footprint fits, so
 //   no hipMalloc happens on the request path.
-// * A worker thread groups all jobs admitted since its last launch into one
-//   batched launch of the engine on the next stream of a small pool; jobs that
-//   arrive while earlier launches run are launched on another stream and
-//   overlap with them on the device.
+// * A worker thread groups the jobs admitted since its last launch into one
+//   batched launch of the engine; jobs that arrive while earlier launches run
+//   are launched on another stream and overlap with them on the device.
+// * Latency: a large job (above kBigCells cells) gets a launch of its own (a
+//   batch completes as a whole, so small jobs batched with a large one would
+//   wait for it).  The streams are split in two classes: large launches use
+//   the first half, small ones the second, each picking the stream of its
+//   class with the least work in flight, so a small launch never queues
+//   behind a large one on a stream.  A large launch runs one persistent
+//   workgroup per compute unit, which leaves workgroup slots free for the
+//   small launches (a persistent grid would hold every slot until the large
+//   job ends) and shortens the large job's own critical path (its strips are
+//   sequential chains of tiles that run faster with fewer waves per SIMD).
 // * Each launch copies its histograms into pinned host buffers (recycled
 //   through a cache) and then fires a host callback that marks its jobs done
 //   and returns their device memory to the pool; the worker then admits more.
@@ -96,6 +105,9 @@ struct ServedJob {
 };
 
 constexpr size_t kMaxBatch = 256;
+constexpr double kBigCells = 2.0e9;   // jobs above this (~45k vectors) launch alone
+
+double job_cells(const ServedJob *j) { return static_cast<double>(j->n_vec) * j->n_vec; }
 constexpr size_t kInfoWords = kInfoBytes / sizeof(uint64_t);
 
 }  // namespace
@@ -112,8 +124,8 @@ struct rqa_server {
     std::vector<char *> launch_scratch;   // per stream, device
     std::vector<void *> staging;          // per stream, pinned host
     std::vector<hipEvent_t> staging_free; // per stream: staging consumed
-    std::vector<AuxStreams> aux;          // per stream: fork streams for mixed groups
-    size_t next_stream = 0;
+    std::vector<double> load;             // per stream: cells of the launches in flight
+    int ncu = 0;                          // compute units of the device
     std::deque<ServedJob *> pending;
     std::unordered_map<uint64_t, ServedJob *> jobs;
     std::multimap<size_t, void *> pinned_free;   // recycled pinned result buffers
@@ -129,6 +141,8 @@ namespace {
 struct Launch {
     rqa_server *srv;
     std::vector<ServedJob *> jobs;
+    size_t slot;
+    double cells;
 };
 
 size_t job_hist_bytes(int64_t n_vec) {
@@ -166,6 +180,7 @@ void on_launch_done(void *arg) {
             j->state = flag ? kFailed : kDone;
             srv->pool.release(j->off, j->footprint);
         }
+        srv->load[ln->slot] -= ln->cells;
         --srv->inflight;
         ++srv->completions;
     }
@@ -174,23 +189,36 @@ void on_launch_done(void *arg) {
     delete ln;
 }
 
-// Launch every admissible queued job (FIFO, stopping at the first that does
-// not fit) as one batched launch.  Entered and left with `lk` held; the HIP
-// calls run with it released.  Returns the number of jobs launched.
+// Launch the next admissible queued jobs (FIFO, stopping at the first that
+// does not fit) as one batched launch: either one large job alone or a run of
+// small ones.  Entered and left with `lk` held; the HIP calls run with it
+// released.  Returns the number of jobs launched.
 size_t admit_and_launch(rqa_server *srv, std::unique_lock<std::mutex> &lk) {
     std::vector<ServedJob *> batch;
+    double cells = 0.0;
     while (!srv->pending.empty() && batch.size() < kMaxBatch) {
         ServedJob *j = srv->pending.front();
+        const bool big = job_cells(j) > kBigCells;
+        if (big && !batch.empty()) break;   // it starts the next launch
         size_t off = 0;
         if (!srv->pool.alloc(j->footprint, &off)) break;
         j->off = off;
         j->state = kRunning;
         srv->pending.pop_front();
         batch.push_back(j);
+        cells += job_cells(j);
+        if (big) break;
     }
     if (batch.empty()) return 0;
-    const size_t slot = srv->next_stream;
-    srv->next_stream = (srv->next_stream + 1) % srv->streams.size();
+    // The stream of the launch's class with the least work in flight.
+    const bool big = batch.size() == 1 && cells > kBigCells;
+    const size_t ns = srv->streams.size();
+    const size_t half = ns > 1 ? ns / 2 : 1;
+    const size_t lo = (big || ns == 1) ? 0 : half, hi = big ? half : ns;
+    size_t slot = lo;
+    for (size_t c = lo + 1; c < hi; ++c)
+        if (srv->load[c] < srv->load[slot]) slot = c;
+    srv->load[slot] += cells;
     ++srv->inflight;
     lk.unlock();
 
@@ -214,7 +242,7 @@ size_t admit_and_launch(rqa_server *srv, std::unique_lock<std::mutex> &lk) {
     }
     if (rc == RQA_OK)
         rc = engine_launch(ej, srv->launch_scratch[slot], srv->staging[slot],
-                           srv->staging_free[slot], 0, st, nullptr, &srv->aux[slot]);
+                           srv->staging_free[slot], big ? srv->ncu : 0, st, nullptr, nullptr);
     for (size_t k = 0; k < batch.size() && rc == RQA_OK; ++k) {
         ServedJob *j = batch[k];
         const size_t hb = sizeof(uint64_t) * 3 * static_cast<size_t>(j->n_vec + 1);
@@ -223,7 +251,7 @@ size_t admit_and_launch(rqa_server *srv, std::unique_lock<std::mutex> &lk) {
                            hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = RQA_EDEVICE;
     }
-    Launch *ln = new Launch{srv, batch};
+    Launch *ln = new Launch{srv, batch, slot, cells};
     if (rc == RQA_OK && hipLaunchHostFunc(st, on_launch_done, ln) == hipSuccess) {
         lk.lock();
         return batch.size();
@@ -237,6 +265,7 @@ size_t admit_and_launch(rqa_server *srv, std::unique_lock<std::mutex> &lk) {
         j->rc = rc == RQA_OK ? RQA_EDEVICE : rc;
         srv->pool.release(j->off, j->footprint);
     }
+    srv->load[slot] -= cells;
     --srv->inflight;
     ++srv->completions;
     srv->done_cv.notify_all();
@@ -312,7 +341,10 @@ int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams) {
     if (!out || budget_bytes < 4096 || streams < 1 || streams > 16) return RQA_EINVAL;
     std::unique_ptr<rqa_server> srv(new (std::nothrow) rqa_server);
     if (!srv) return RQA_ENOMEM;
-    if (hipGetDevice(&srv->device) != hipSuccess) return RQA_EDEVICE;
+    if (hipGetDevice(&srv->device) != hipSuccess ||
+        hipDeviceGetAttribute(&srv->ncu, hipDeviceAttributeMultiprocessorCount, srv->device) !=
+            hipSuccess)
+        return RQA_EDEVICE;
     void *base = nullptr;
     if (hipMalloc(&base, budget_bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -335,8 +367,7 @@ int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams) {
         hipEvent_t ev = nullptr;
         ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
         if (ok) srv->staging_free.push_back(ev);
-        srv->aux.emplace_back();
-        ok = ok && srv->aux.back().create(3) == RQA_OK;
+        srv->load.push_back(0.0);
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -344,7 +375,6 @@ int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams) {
         for (char *d : srv->launch_scratch) hipFree(d);
         for (void *h : srv->staging) hipHostFree(h);
         for (hipEvent_t e : srv->staging_free) hipEventDestroy(e);
-        for (AuxStreams &a : srv->aux) a.destroy();
         hipFree(base);
         return RQA_ENOMEM;
     }
@@ -456,10 +486,6 @@ void rqa_server_destroy(rqa_server *srv) {
     for (char *d : srv->launch_scratch) hipFree(d);
     for (void *h : srv->staging) hipHostFree(h);
     for (hipEvent_t e : srv->staging_free) hipEventDestroy(e);
-    for (AuxStreams &a : srv->aux) {
-        for (int k = 0; k < a.count; ++k) hipStreamSynchronize(a.s[k]);
-        a.destroy();
-    }
     for (auto &kv : srv->jobs) {
         hipHostFree(kv.second->host);
         hipEventDestroy(kv.second->ready);
