@@ -211,10 +211,19 @@ def bench_cpu_baseline(args, hl):
     t0 = time.perf_counter()
     oracle.histograms(s, p.m, p.tau, p.eps, p.norm, p.theiler, threads=threads)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, on a tenth of the sample
+    s1 = hl["series"][: max(args.cpu_points // 10, 1000)]
+    n1 = len(s1) - (p.m - 1) * p.tau
+    t1 = time.perf_counter()
+    oracle.histograms(s1, p.m, p.tau, p.eps, p.norm, p.theiler, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": round(float(n) * n / dt / 1e9, 4), "unit": "Gcells/s", "cores": threads,
             "kind": "oracle", "seconds": round(dt, 2),
             "sample": f"first {len(s)} points of the same Lorenz series (n_vec={n}), "
-                      f"full matrix, {threads} threads, {cpu_model()}"}
+                      f"full matrix, {threads} threads, {cpu_model()}",
+            "single_thread": {"value": round(float(n1) * n1 / dt1 / 1e9, 4), "unit": "Gcells/s",
+                              "seconds": round(dt1, 2),
+                              "sample": f"first {len(s1)} points, 1 thread"}}
 
 
 def bench_batched(args, torch, RQA, workload, windows_plan):
