@@ -50,6 +50,32 @@ def test_mixed_stream_equals_alone(cuda, oracle_lib):
             assert all(np.array_equal(x, y) for x, y in zip((got.diag, got.vert, got.white), ref))
 
 
+@pytest.mark.parametrize("streams", [1, 2, 3, 4])
+def test_large_jobs_mixed_with_small(streams, cuda):
+    """Large jobs (launched alone, one workgroup per compute unit, on their own
+    stream class) interleaved with small ones give the results they give alone."""
+    import torch
+    from paper_2402_16853_amd import RQA, Server
+    rng = np.random.default_rng(40 + streams)
+    jobs = []
+    for k in range(14):
+        big = k % 4 == 1
+        n = int(rng.integers(48_000, 70_000)) if big else int(rng.integers(500, 9_000))
+        x = np.cumsum(rng.normal(size=n)).astype(np.float32) * 0.05
+        p = Params(m=int(rng.integers(2, 5)), tau=int(rng.integers(1, 4)),
+                   eps=float(rng.uniform(0.05, 0.3)), norm=int(rng.integers(1, 4)), theiler=1)
+        jobs.append((p, torch.from_numpy(x).to(cuda)))
+    torch.cuda.synchronize()
+    srv = Server(8 << 30, streams=streams)
+    _announce("serve-large-mixed", streams=streams, jobs=len(jobs),
+              large=sum(1 for p, d in jobs if d.numel() >= 48_000))
+    tickets = [srv.submit(p, d) for p, d in jobs]
+    served = [srv.wait(t) for t in tickets]
+    srv.close()
+    for k, ((p, d), got) in enumerate(zip(jobs, served)):
+        same(got, RQA.from_params(p)(d), f"streams {streams} job {k} n={d.numel()}")
+
+
 def test_budget_admission(cuda):
     import torch
     from paper_2402_16853_amd import Server, RQAError
