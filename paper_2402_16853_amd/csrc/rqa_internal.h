@@ -17,6 +17,9 @@ struct KParams {
     int32_t tau;
     float eps;      // L1 / Linf threshold
     float eps_sq;   // fl32(eps*eps), L2 threshold on the squared sum
+    float d0_bound; // |d_0| above this makes a pair non-recurrent whatever the
+                    // other coordinates (L1, Linf: eps; L2: the largest t with
+                    // fl32(t*t) <= eps_sq)
     int32_t norm;
     int32_t theiler;
     int32_t lmin, vmin, wmin;   // minimum diagonal / vertical / white line lengths

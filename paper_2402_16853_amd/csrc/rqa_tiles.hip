@@ -33,7 +33,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "rqa_internal.h"
@@ -47,6 +49,29 @@ KParams make_kparams(const rqa_params &p) {
     k.eps = p.eps;
     volatile float e = p.eps;   // one FP32 rounding of eps*eps, no contraction
     k.eps_sq = e * e;
+    // First-coordinate bound.  The accumulated distance a never falls below the
+    // first coordinate's term (a sum or max of non-negative terms, and rounding
+    // is monotone), and that term is monotone in |d_0|, so |d_0| > d0_bound
+    // decides "not recurrent" exactly.
+    if (p.norm != RQA_NORM_L2) {
+        k.d0_bound = p.eps;
+    } else if (!std::isfinite(k.eps_sq)) {
+        k.d0_bound = std::numeric_limits<float>::infinity();
+    } else {
+        // Largest t >= 0 with fl32(t*t) <= eps_sq: binary search over the bit
+        // patterns of non-negative floats, which are ordered like the values
+        // (fl32(0*0) = 0 <= eps_sq; fl32(inf*inf) = inf > eps_sq).
+        uint32_t lo = 0u, hi = 0x7F800000u;
+        while (hi - lo > 1u) {
+            const uint32_t mid = lo + (hi - lo) / 2u;
+            float t;
+            std::memcpy(&t, &mid, sizeof t);
+            volatile float tv = t;
+            volatile float sq = tv * tv;
+            if (sq <= k.eps_sq) lo = mid; else hi = mid;
+        }
+        std::memcpy(&k.d0_bound, &lo, sizeof lo);
+    }
     k.norm = p.norm;
     k.theiler = p.theiler;
     k.lmin = p.lmin;
@@ -93,6 +118,7 @@ struct JobDesc {
     int32_t mode;              // JobMode
     int32_t m, tau, norm, theiler, wp;
     float thr;                 // eps (L1, Linf) or fl32(eps*eps) (L2)
+    float thr0;                // first-coordinate bound (KParams::d0_bound)
     int32_t H;                 // strip height
     int32_t nstrips;
     int32_t c_last;            // last column tile (nb-1)/64
@@ -354,6 +380,30 @@ __device__ __forceinline__ uint32_t nonrec_sign(ConstF col, int tau, const float
     return __float_as_uint(thr - a);
 }
 
+// The same, with the first coordinate's difference d0 = col[0] - xr[0] given.
+template <int NORM, int M>
+__device__ __forceinline__ uint32_t nonrec_sign_d0(float d0, ConstF col, int tau, const float *xr,
+                                                   float thr) {
+    float a;
+    if (NORM == RQA_NORM_L1) {
+        a = fabsf(d0);
+#pragma unroll
+        for (int k = 1; k < M; ++k) a = a + fabsf(col[k * tau] - xr[k]);
+    } else if (NORM == RQA_NORM_L2) {
+        a = d0 * d0;
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+            const float e = col[k * tau] - xr[k];
+            a = a + e * e;
+        }
+    } else {
+        a = fabsf(d0);
+#pragma unroll
+        for (int k = 1; k < M; ++k) a = fmaxf(a, fabsf(col[k * tau] - xr[k]));
+    }
+    return __float_as_uint(thr - a);
+}
+
 // Generic embedding dimension: row coordinates read from memory.
 template <int NORM>
 __device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__restrict__ rowp,
@@ -382,18 +432,21 @@ __device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__r
 // columns are taken in eight chunks of 8 (highest first), each fully unrolled,
 // so that at most 8*m column coordinates are live in SGPRs (chunks of 16 left
 // too few SGPRs for the rest of the kernel, which then spilled into VGPR lanes;
-// measured 10% slower).
+// measured 10% slower).  Each chunk first takes the first coordinate's
+// differences: when no lane of the wave has |d_0| <= thr0 in the chunk, all
+// 8 x 64 pairs are non-recurrent (the bound is exact, see KParams::d0_bound)
+// and the other coordinates are not evaluated.
 template <int NORM, int M>
 __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
                                           const float *__restrict__ rowp, int m, float thr_s,
-                                          uint32_t &lo, uint32_t &hi) {
-    // The threshold is uniform, but as a scalar operand it would make the last
-    // subtraction read an SGPR too; VALU instructions with only VGPR operands
-    // issue faster on gfx950 (measured: the six-instruction L-infinity column
-    // sustains ~1.5 instead of ~1.2 wave-instructions per clock per CU).  The
-    // empty asm pins the copy in a VGPR.
-    float thr = thr_s;
-    asm volatile("" : "+v"(thr));
+                                          float thr0_s, uint32_t &lo, uint32_t &hi) {
+    // The thresholds are uniform, but as scalar operands they would make the
+    // subtraction and the compare read an SGPR too; VALU instructions with only
+    // VGPR operands issue faster on gfx950 (measured: the six-instruction
+    // L-infinity column sustains ~1.5 instead of ~1.2 wave-instructions per
+    // clock per CU).  The empty asm pins the copies in VGPRs.
+    float thr = thr_s, thr0 = thr0_s;
+    asm volatile("" : "+v"(thr), "+v"(thr0));
 #pragma unroll 1
     for (int half = 1; half >= 0; --half) {
         uint32_t acc = 0;
@@ -402,9 +455,32 @@ __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
             const int b0 = half * 32 + sub * 8;
             ConstF cb = cols + b0;
             if (M > 0) {
+                // All of the chunk's coordinates are loaded up front (the empty
+                // asm keeps the compiler from sinking the loads of the other
+                // coordinates into the branch, which would add a second wait);
+                // the first coordinate's differences decide whether the rest
+                // is evaluated.
+                float d0[8];
 #pragma unroll
-                for (int b = 7; b >= 0; --b)
-                    acc = __builtin_amdgcn_alignbit(acc, nonrec_sign<NORM, M>(cb + b, tau, xr, thr), 31);
+                for (int b = 0; b < 8; ++b) {
+                    d0[b] = cb[b] - xr[0];
+#pragma unroll
+                    for (int k = 1; k < (M > 0 ? M : 1); ++k) {
+                        const float ck = cb[b + k * tau];
+                        asm volatile("" ::"s"(ck));
+                    }
+                }
+                const float near =
+                    fminf(fminf(fminf(fabsf(d0[0]), fabsf(d0[1])), fminf(fabsf(d0[2]), fabsf(d0[3]))),
+                          fminf(fminf(fabsf(d0[4]), fabsf(d0[5])), fminf(fabsf(d0[6]), fabsf(d0[7]))));
+                if (__builtin_amdgcn_ballot_w64(near <= thr0) == 0ull) {
+                    acc = (acc << 8) | 0xFFu;
+                } else {
+#pragma unroll
+                    for (int b = 7; b >= 0; --b)
+                        acc = __builtin_amdgcn_alignbit(
+                            acc, nonrec_sign_d0<NORM, M>(d0[b], cb + b, tau, xr, thr), 31);
+                }
             } else {
                 for (int b = 7; b >= 0; --b)
                     acc = __builtin_amdgcn_alignbit(
@@ -579,7 +655,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                 xhi = (uint32_t)(word >> 32);
             } else {
                 const ConstF cols = to_const((c == j.c_last) ? j.tail : j.sb + jbase);
-                tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, xlo, xhi);
+                tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, j.thr0, xlo, xhi);
             }
 
             // Interior tile: no cell needs masking, and every column and
@@ -1170,7 +1246,7 @@ struct PlotDesc {
     int64_t words;             // 64-bit words per output row
     int64_t nb_points;         // points of b
     int32_t n, nb, m, tau, theiler;
-    float thr;
+    float thr, thr0;
     int32_t row_tiles, col_tiles, chunks, cross;
     int32_t tail_len;
 };
@@ -1204,7 +1280,7 @@ __global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
         const int jbase = c * 64;
         const ConstF cols = to_const(c == d.col_tiles - 1 ? d.tail : d.b + jbase);
         uint32_t xlo, xhi;
-        tile_bits<NORM, M>(cols, d.tau, xr, rowp, d.m, d.thr, xlo, xhi);
+        tile_bits<NORM, M>(cols, d.tau, xr, rowp, d.m, d.thr, d.thr0, xlo, xhi);
         uint64_t vm = 0ull;
         if (i < n) {
             const int hv = nb - jbase < 64 ? nb - jbase : 64;
@@ -1451,6 +1527,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         d.theiler = kp.theiler;
         d.wp = kp.theiler > 1 ? kp.theiler : 1;
         d.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
+        d.thr0 = kp.d0_bound;
         d.H = lay.H;
         d.nstrips = lay.nstrips;
         d.c_last = (int32_t)((ncols - 1) / 64);
@@ -1548,6 +1625,7 @@ int engine_plot(const KParams &kp, const float *a, int64_t na_points, const floa
     pd.tau = kp.tau;
     pd.theiler = kp.theiler;
     pd.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
+    pd.thr0 = kp.d0_bound;
     pd.row_tiles = (int32_t)((n + 63) / 64);
     pd.col_tiles = (int32_t)((nb + 63) / 64);
     pd.chunks = (pd.col_tiles + kPlotChunk - 1) / kPlotChunk;

@@ -129,3 +129,21 @@ def test_lines_through_empty_tile_corners(waves, cuda, oracle_lib):
         _announce("corner_lines", waves=waves, norm=norm, m=m, n=len(s))
         assert_same(run_gpu(s, p, cuda, waves=waves), *oracle_lib.rqa(s, p),
                     tag=f"corner lines waves {waves} norm {norm} m {m}")
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-30, 1e-23, 2.5e-23, 3e-23, 0.3, 1e19, 3e19])
+def test_l2_threshold_extremes(eps, cuda, oracle_lib):
+    """Euclidean thresholds whose square underflows, sits at the rounding
+    boundary or overflows: the first-coordinate bound that lets the kernel skip
+    the other coordinates must agree with the full predicate everywhere."""
+    import time
+    rng = np.random.default_rng(5)
+    base = (np.arange(1500) % 7).astype(np.float64)
+    s = base + np.where(rng.random(1500) < 0.3, rng.normal(size=1500) * 1e-23, 0.0)
+    s = np.concatenate([s, rng.normal(size=600) * 1e18]).astype(np.float32)
+    p = Params(m=3, tau=2, eps=eps, norm=2, theiler=1)
+    _announce("l2_extremes", eps=eps, n=len(s))
+    t0 = time.perf_counter()
+    res = run_gpu(s, p, cuda, waves=4)
+    assert time.perf_counter() - t0 < 30.0
+    assert_same(res, *oracle_lib.rqa(s, p), tag=f"L2 eps={eps}")
