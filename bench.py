@@ -82,6 +82,22 @@ def measured_traffic():
         return None
 
 
+def measured_pruning(achieved_tops, ops_per_pair):
+    """Share of 8-column chunks whose predicate the tile kernel evaluated in full
+    (the rest are decided by the first coordinate alone), from the committed
+    counter summary, and the rate of the operations actually executed."""
+    try:
+        full = float(profile_fields()["full-evaluation chunk fraction"])
+    except (KeyError, ValueError):
+        return None
+    # per pair: all ops_per_pair in a full chunk; in a pruned chunk one
+    # subtraction and one comparison (the wave-wide minimum test)
+    executed = full * ops_per_pair + (1.0 - full) * 2.0
+    return {"full_chunk_frac": full, "executed_ops_per_pair": round(executed, 3),
+            "executed_tops": round(achieved_tops * executed / ops_per_pair, 3),
+            "executed_frac": round(achieved_tops * executed / ops_per_pair / VALU_PEAK_TOPS, 4)}
+
+
 def measured_lds(kernel_ms):
     """LDS throughput of k_tiles: the committed per-launch LDS bytes over this
     run's kernel time, against the probed LDS read peak (None if stale)."""
@@ -186,6 +202,7 @@ def bench_headline(args, torch, RQA, workload):
             "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
             "traffic": measured_traffic(),
             "lds": measured_lds(tile_ms),
+            "pruning": measured_pruning(achieved, ops_per_pair(p.m, p.norm)),
             "frac_vs_64_lanes": round(achieved / (VALU_PEAK_TOPS / 2), 4),
             "predicate_ceiling": {"tops": PREDICATE_CEILING_TOPS,
                                   "frac": round(achieved / PREDICATE_CEILING_TOPS, 4),
