@@ -226,7 +226,10 @@ const char *rqa_strerror(int code);
 typedef struct rqa_server rqa_server;
 
 /* budget_bytes: device memory the server may hold for job workspaces;
- * streams: concurrent launch slots (1..16). */
+ * streams: concurrent launch slots (1..16).  With two or more streams, the
+ * first half runs large jobs (above 2e9 matrix cells, each launched alone)
+ * and the second half batches of small ones, so small jobs never queue behind
+ * a large one; with one stream everything shares it. */
 int rqa_server_create(rqa_server **out, size_t budget_bytes, int32_t streams);
 
 /* Device bytes of the server pool a job of n_points occupies while it runs
