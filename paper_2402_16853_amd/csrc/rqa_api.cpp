@@ -471,23 +471,43 @@ int fetch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag, uint6
     if (flag & 1) return RQA_ENONFINITE;
     if (flag) return RQA_EDEVICE;   // internal consistency check failed on the device
     if (diag || vert || white) {
+        // Entries above a histogram's longest line are zero (the device
+        // statistics hold the longest lines), so only the prefixes cross PCIe
+        // and the tails are cleared on the host.  A launch of one job copies
+        // its three prefixes; a batch copies the block of all its jobs once.
+        JobStats st;
+        std::memcpy(&st, info + 8, sizeof st);
+        int64_t used[3];
+        for (int k = 0; k < 3; ++k)
+            used[k] = std::min<int64_t>(hl, static_cast<int64_t>(st.longest[k]) + 1);
+        const bool single = h->nvec.size() == 1;
         if (!h->cache_valid) {
             int rc = grow(reinterpret_cast<void **>(&h->host_cache), &h->host_cache_bytes,
                           h->hist_block_bytes);
             if (rc != RQA_OK) return rc;
-            if (hipMemcpyAsync(h->host_cache,
-                               static_cast<const char *>(h->ws.base) + h->hist_block_off,
-                               h->hist_block_bytes, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
-                hipStreamSynchronize(h->stream) != hipSuccess)
-                return RQA_EDEVICE;
+            const char *dev = static_cast<const char *>(h->ws.base) + h->hist_block_off;
+            bool ok = true;
+            if (single) {
+                for (int k = 0; k < 3 && ok; ++k)
+                    ok = hipMemcpyAsync(reinterpret_cast<char *>(h->host_cache) +
+                                            sizeof(uint64_t) * k * hl,
+                                        dev + sizeof(uint64_t) * k * hl, sizeof(uint64_t) * used[k],
+                                        hipMemcpyDeviceToHost, h->stream) == hipSuccess;
+            } else {
+                ok = hipMemcpyAsync(h->host_cache, dev, h->hist_block_bytes, hipMemcpyDeviceToHost,
+                                    h->stream) == hipSuccess;
+            }
+            if (!ok || hipStreamSynchronize(h->stream) != hipSuccess) return RQA_EDEVICE;
             h->cache_valid = true;
         }
         const uint64_t *hd = reinterpret_cast<const uint64_t *>(
             reinterpret_cast<const char *>(h->host_cache) + (h->job_off[index] - h->hist_block_off));
-        const uint64_t *hv = hd + hl, *hw = hv + hl;
-        if (diag) std::memcpy(diag, hd, sizeof(uint64_t) * hl);
-        if (vert) std::memcpy(vert, hv, sizeof(uint64_t) * hl);
-        if (white) std::memcpy(white, hw, sizeof(uint64_t) * hl);
+        uint64_t *dst[3] = {diag, vert, white};
+        for (int k = 0; k < 3; ++k) {
+            if (!dst[k]) continue;
+            std::memcpy(dst[k], hd + k * hl, sizeof(uint64_t) * used[k]);
+            std::memset(dst[k] + used[k], 0, sizeof(uint64_t) * (hl - used[k]));
+        }
     }
     if (out) {
         JobStats st;
