@@ -107,11 +107,10 @@ struct JobDesc {
     unsigned long long *hw;
     int *flag;                 // non-finite flag
     uint32_t *lead;            // leading run of each row of U: len | color<<31
-    // Strip-edge summaries, one u32 per (strip, line): the low half holds the
-    // first run and the high half the last one, written separately (by the
-    // waves that finish them) and read together by the stitch.
-    uint32_t *vsum;            // per (strip, column): run len | color<<15
-    uint32_t *dsum;            // per (strip, diagonal): black run at the top / bottom edge
+    uint16_t *vfirst;          // per (strip, column): first run len | color<<15
+    uint16_t *vlast;           // per (strip, column): last run len | color<<15
+    uint16_t *dfirst;          // per (strip, diagonal): black run at the top edge
+    uint16_t *dlast;           // per (strip, diagonal): black run at the bottom edge
     int64_t n_points;
     int32_t n;                 // delay vectors (rows)
     int32_t nb;                // columns (auto: n)
@@ -243,13 +242,6 @@ __device__ __forceinline__ void g_add(unsigned long long *p, unsigned long long 
 __device__ __forceinline__ void g_or(int *p, int v) {
     __hip_atomic_fetch_or(glb(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// The two halves of a strip-edge summary word.
-__device__ __forceinline__ void put_first(uint32_t *sum, int64_t idx, uint16_t v) {
-    *glb(reinterpret_cast<uint16_t *>(sum) + 2 * idx) = v;
-}
-__device__ __forceinline__ void put_last(uint32_t *sum, int64_t idx, uint16_t v) {
-    *glb(reinterpret_cast<uint16_t *>(sum) + 2 * idx + 1) = v;
-}
 
 struct Bins {
     uint32_t *d, *v, *w;
@@ -286,13 +278,13 @@ __device__ __forceinline__ void finish_run(const LineCtx &lc, uint32_t c, uint32
     const JobDesc &j = *lc.jd;
     if (KIND == kDiag) {
         if (first) {
-            if (lc.sum_ok) put_first(j.dsum, lc.sum_idx, (uint16_t)(c ? len : 0u));
+            if (lc.sum_ok) *glb(j.dfirst + lc.sum_idx) = (uint16_t)(c ? len : 0u);
         } else if (c) {
             emit(lc.bins.d, kCapD, j.hd, len, (uint32_t)DW, (uint32_t)j.hmax, j.flag);
         }
     } else if (KIND == kVert) {
         if (first)
-            put_first(j.vsum, lc.sum_idx, (uint16_t)(len | (c << 15)));
+            *glb(j.vfirst + lc.sum_idx) = (uint16_t)(len | (c << 15));
         else if (c)
             emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
         else
@@ -739,8 +731,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     }
                     if (wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
-                        put_last(j.vsum, sidx, pk);
-                        if (st.first) put_first(j.vsum, sidx, pk);
+                        *glb(j.vlast + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;
                     } else {
                         L.vs(slot, wave, lane) = pack_run(st);
                     }
@@ -752,7 +744,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     const int klo = kup - 64;
                     Run up;
                     if (wave == 0) {
-                        if (!FULL || dok(kup)) put_first(j.dsum, dbase + kup, 0);   // white first cell
+                        if (!FULL || dok(kup)) *glb(j.dfirst + dbase + kup) = 0;   // white first cell
                         up = Run{0u, 0u, 0u};
                     } else {
                         up = unpack_run(L.ds(slot, wave - 1, lane));
@@ -774,8 +766,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                         L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (!FULL || dok(klo)) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        put_last(j.dsum, dbase + klo, b);
-                        if (lw.first) put_first(j.dsum, dbase + klo, b);
+                        *glb(j.dlast + dbase + klo) = b;
+                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
                     }
                     left = up;
                 }
@@ -816,8 +808,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     run_segment<kVert>(Y, vwin, 0u, vhi, st, lc);
                     if (e <= 63 || wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
-                        put_last(j.vsum, sidx, pk);
-                        if (st.first) put_first(j.vsum, sidx, pk);
+                        *glb(j.vlast + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;
                     } else {
                         L.vs(slot, wave, lane) = pack_run(st);
                     }
@@ -847,7 +839,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     // does not matter).
                     up = Run{(uint32_t)(D & 1ull), 0u, 1u};
                     if (!up.color) {
-                        if (dok(kup)) put_first(j.dsum, dbase + kup, 0);
+                        if (dok(kup)) *glb(j.dfirst + dbase + kup) = 0;
                         up.first = 0;
                     }
                 } else if (jbase + q > nb - 1) {
@@ -876,8 +868,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                         L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (ok) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        put_last(j.dsum, dbase + klo, b);
-                        if (lw.first) put_first(j.dsum, dbase + klo, b);
+                        *glb(j.dlast + dbase + klo) = b;
+                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
                     }
                 }
                 left = up;
@@ -974,18 +966,21 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
         const int col = (int)line;
         uint32_t oc = 0, ol = 0;
         for (int s0 = 0; s0 < S; s0 += kStitchBatch) {
-            uint32_t sv[kStitchBatch];
+            uint32_t fv[kStitchBatch], lv[kStitchBatch];
 #pragma unroll
             for (int u = 0; u < kStitchBatch; ++u) {
                 const int64_t idx = (int64_t)(s0 + u) * nb + col;
-                if (s0 + u < S) sv[u] = *glb(j.vsum + idx);
+                if (s0 + u < S) {
+                    fv[u] = *glb(j.vfirst + idx);
+                    lv[u] = *glb(j.vlast + idx);
+                }
             }
 #pragma unroll
             for (int u = 0; u < kStitchBatch; ++u) {
                 const int s = s0 + u;
                 if (s >= S) break;
                 const uint32_t Ls = s < S - 1 ? (uint32_t)H : (uint32_t)(n - s * H);
-                const uint32_t f = sv[u] & 0xFFFFu, l = sv[u] >> 16;
+                const uint32_t f = fv[u], l = lv[u];
                 const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
                 if (fl == Ls) {   // the segment is one run
                     if (ol && oc == fc) ol += Ls;
@@ -1008,13 +1003,10 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
         for (int s = sf; s <= sl; ++s) {
             const int64_t idx = (int64_t)s * (nb + H - 1) + (k + s * H + H - 1);
             const bool top = s > sf || r0 == s * H;
-            // The first-run half is not written where the diagonal starts
-            // inside the strip (no top edge); it is not used there.
-            const uint32_t w = (top || s < sl) ? *glb(j.dsum + idx) : 0u;
-            const uint32_t fb = top ? (w & 0xFFFFu) : 0u;
+            const uint32_t fb = top ? (uint32_t)*glb(j.dfirst + idx) : 0u;
             if (s < sl && top && fb == (uint32_t)H) { open += H; continue; }
             if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 1u, (uint32_t)j.hmax, j.flag);
-            open = s < sl ? (w >> 16) : 0u;
+            open = s < sl ? (uint32_t)*glb(j.dlast + idx) : 0u;
         }
     }
 }
@@ -1048,13 +1040,14 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
             // The summaries of kStitchBatch strips are loaded before any is
             // folded, so a thread has that many loads in flight.
             for (int s0 = 0; s0 <= s_last; s0 += kStitchBatch) {
-                uint32_t sv[kStitchBatch];
+                uint32_t fv[kStitchBatch], lv[kStitchBatch];
 #pragma unroll
                 for (int u = 0; u < kStitchBatch; ++u) {
                     const int s = s0 + u;
                     if (s <= s_last) {
                         const int64_t idx = strip_offset(s, n, wp, H) + (col - s * H - wp);
-                        sv[u] = *glb(j.vsum + idx);
+                        fv[u] = *glb(j.vfirst + idx);
+                        lv[u] = *glb(j.vlast + idx);
                     }
                 }
 #pragma unroll
@@ -1062,7 +1055,7 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
                     const int s = s0 + u;
                     if (s > s_last) break;
                     const uint32_t Ls = s < s_last ? (uint32_t)H : (uint32_t)(col - wp - s * H + 1);
-                    const uint32_t f = sv[u] & 0xFFFFu, l = sv[u] >> 16;
+                    const uint32_t f = fv[u], l = lv[u];
                     const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
                     if (fl == Ls) {   // the segment is one run
                         if (ol && oc == fc) ol += Ls;
@@ -1102,23 +1095,24 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
             const int s_last = (n - 1 - k) / H;
             uint32_t open = 0;
             for (int s0 = 0; s0 <= s_last; s0 += kStitchBatch) {
-                uint32_t sv[kStitchBatch];
+                uint32_t fv[kStitchBatch], lv[kStitchBatch];
 #pragma unroll
                 for (int u = 0; u < kStitchBatch; ++u) {
                     const int s = s0 + u;
                     if (s <= s_last) {
                         const int64_t idx = strip_offset(s, n, wp, H) + (k - wp);
-                        sv[u] = *glb(j.dsum + idx);
+                        fv[u] = *glb(j.dfirst + idx);
+                        lv[u] = *glb(j.dlast + idx);
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < kStitchBatch; ++u) {
                     const int s = s0 + u;
                     if (s > s_last) break;
-                    const uint32_t fb = sv[u] & 0xFFFFu;
+                    const uint32_t fb = fv[u];
                     if (s < s_last && fb == (uint32_t)H) { open += H; continue; }
                     if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
-                    open = s < s_last ? sv[u] >> 16 : 0u;
+                    open = s < s_last ? lv[u] : 0u;
                 }
             }
         } else if (k == 0 && j.theiler == 0) {
@@ -1362,10 +1356,10 @@ int group_key(const Job &jb) {
 
 struct Layout {
     int H, nstrips;
-    int64_t ventries;      // vertical summary words (first and last run)
-    int64_t dentries;      // diagonal summary words
+    int64_t ventries;      // vertical summary entries per array (first, last)
+    int64_t dentries;      // diagonal summary entries per array
     int64_t tail_len;
-    size_t off_tail, off_lead, off_vs, off_ds, off_ent, bytes;
+    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, bytes;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1401,8 +1395,10 @@ Layout layout_of(const Job &jb) {
     size_t off = 0;
     L.off_tail = off; off += a256(sizeof(float) * (size_t)L.tail_len);
     L.off_lead = off; off += a256(sizeof(uint32_t) * (size_t)lead);
-    L.off_vs = off; off += a256(sizeof(uint32_t) * (size_t)L.ventries);
-    L.off_ds = off; off += a256(sizeof(uint32_t) * (size_t)L.dentries);
+    L.off_vf = off; off += a256(sizeof(uint16_t) * (size_t)L.ventries);
+    L.off_vl = off; off += a256(sizeof(uint16_t) * (size_t)L.ventries);
+    L.off_df = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
+    L.off_dl = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
     L.off_ent = off; off += a256(sizeof(double) * 3 * kStatMaxBlocks);
     L.bytes = off;
     return L;
@@ -1516,8 +1512,10 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         d.hw = d.hv + hlen;
         d.flag = jb.flag;
         d.lead = reinterpret_cast<uint32_t *>(scr + lay.off_lead);
-        d.vsum = reinterpret_cast<uint32_t *>(scr + lay.off_vs);
-        d.dsum = reinterpret_cast<uint32_t *>(scr + lay.off_ds);
+        d.vfirst = reinterpret_cast<uint16_t *>(scr + lay.off_vf);
+        d.vlast = reinterpret_cast<uint16_t *>(scr + lay.off_vl);
+        d.dfirst = reinterpret_cast<uint16_t *>(scr + lay.off_df);
+        d.dlast = reinterpret_cast<uint16_t *>(scr + lay.off_dl);
         d.n_points = jb.n_points;
         d.n = (int32_t)jb.n_vec;
         d.nb = (int32_t)ncols;
