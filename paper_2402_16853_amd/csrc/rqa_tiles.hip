@@ -91,6 +91,8 @@ constexpr int kRing = 4;       // carry slots per pair of consecutive waves (til
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls (~28 ms) before a neighbour wait gives up
 constexpr int kStitchThreads = 256;
 constexpr int kStitchBatch = 8;   // strips whose summaries a stitch thread loads at once
+constexpr int kStitchCapV = 2048; // stitch LDS bins for vertical lengths < kStitchCapV (the
+                                  // stitch joins the runs that cross strip edges: long ones)
 constexpr int kStatThreads = 256;
 constexpr int kStatMaxBlocks = 64;
 
@@ -946,15 +948,52 @@ k_tiles(const JobDesc *__restrict__ jobs, const GroupDesc *__restrict__ groups, 
 // ---------------------------------------------------------------------------
 struct StitchLds {
     uint32_t bd[kCapD];
-    uint32_t bv[kCapV];
+    uint32_t bv[kStitchCapV];
     uint32_t bw[kCapW];
 };
+
+// Global histogram add in which the active lanes of the wave that add to the
+// same bin are combined into one atomic (64-bit atomics on one address
+// serialise in L2; in the stitch, neighbouring lines of a smooth series end long
+// runs of equal length together).
+__device__ __forceinline__ void g_add_combined(unsigned long long *p, uint32_t w) {
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    // At most 64 rounds: each retires at least the first active lane (its own
+    // address matches); the bound keeps a wave from spinning whatever happens.
+    for (int round = 0; round < 64; ++round) {
+        // readfirstlane returns int: go through uint32_t so that the low half
+        // is not sign-extended into the high one.
+        const uint32_t lo0 = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+        const uint32_t hi0 = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+        const uint64_t a0 = ((uint64_t)hi0 << 32) | (uint64_t)lo0;
+        // The ballot is taken by every active lane, before the branch.
+        const uint64_t same = __builtin_amdgcn_ballot_w64(a == a0);
+        if (a == a0) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(same >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)same, 0u));
+            if (below == 0u)
+                g_add(p, (unsigned long long)w * (unsigned long long)__builtin_popcountll(same));
+            break;
+        }
+    }
+}
+
+// Stitch emission: LDS bin below the cap, else the combined global add.
+__device__ __forceinline__ void emit_stitch(uint32_t *bins, int cap, unsigned long long *glob,
+                                            uint32_t len, uint32_t wt, uint32_t n, int *flag) {
+    if (len < (uint32_t)cap && len <= n)
+        atomicAdd(bins + len, wt);
+    else if (len <= n)
+        g_add_combined(glob + len, wt);
+    else
+        g_or(flag, 2);
+}
 
 __device__ __forceinline__ void emit_line(StitchLds &L, const JobDesc &j, uint32_t color,
                                           uint32_t len) {
     if (len == 0) return;
-    if (color) emit(L.bv, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
-    else emit(L.bw, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
+    if (color) emit_stitch(L.bv, kStitchCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
+    else emit_stitch(L.bw, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
 }
 
 // Stitch of a full (not symmetric) matrix: lines [0, nb) are the columns, lines
@@ -1005,7 +1044,7 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
             const bool top = s > sf || r0 == s * H;
             const uint32_t fb = top ? (uint32_t)*glb(j.dfirst + idx) : 0u;
             if (s < sl && top && fb == (uint32_t)H) { open += H; continue; }
-            if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 1u, (uint32_t)j.hmax, j.flag);
+            if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 1u, (uint32_t)j.hmax, j.flag);
             open = s < sl ? (uint32_t)*glb(j.dlast + idx) : 0u;
         }
     }
@@ -1014,9 +1053,10 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
 __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__restrict__ jobs,
                                                            int njobs) {
     __shared__ StitchLds L;
+    static_assert(kStitchCapV <= kCapW, "bins are cleared and flushed in one pass over kCapW");
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
         if (t < kCapD) L.bd[t] = 0;
-        if (t < kCapV) L.bv[t] = 0;
+        if (t < kStitchCapV) L.bv[t] = 0;
         L.bw[t] = 0;
     }
     __syncthreads();
@@ -1111,7 +1151,7 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
                     if (s > s_last) break;
                     const uint32_t fb = fv[u];
                     if (s < s_last && fb == (uint32_t)H) { open += H; continue; }
-                    if (open + fb) emit(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
+                    if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
                     open = s < s_last ? lv[u] : 0u;
                 }
             }
@@ -1124,7 +1164,7 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
     const int hl = n + 1;
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
         if (t < kCapD && L.bd[t] && t < hl) g_add(j.hd + t, (unsigned long long)L.bd[t]);
-        if (t < kCapV && L.bv[t] && t < hl) g_add(j.hv + t, (unsigned long long)L.bv[t]);
+        if (t < kStitchCapV && L.bv[t] && t < hl) g_add(j.hv + t, (unsigned long long)L.bv[t]);
         if (L.bw[t] && t < hl) g_add(j.hw + t, (unsigned long long)L.bw[t]);
     }
 }
