@@ -147,3 +147,21 @@ def test_l2_threshold_extremes(eps, cuda, oracle_lib):
     res = run_gpu(s, p, cuda, waves=4)
     assert time.perf_counter() - t0 < 30.0
     assert_same(res, *oracle_lib.rqa(s, p), tag=f"L2 eps={eps}")
+
+
+@pytest.mark.parametrize("case", ["constant_5000", "sine_24000"])
+def test_long_runs_across_strips(case, cuda, oracle_lib):
+    """Runs longer than the stitch's LDS bins, ended together by neighbouring
+    lines (a constant series: every vertical run spans the column; a slow sine:
+    runs of ~500-1,100 rows crossing strip edges in step): the global-atomic
+    path that combines equal lengths within a wave."""
+    if case == "constant_5000":
+        s = np.full(5000, 0.5, dtype=np.float32)
+        p = Params(m=2, tau=1, eps=0.0, norm=3, theiler=1)
+    else:
+        s = np.sin(np.linspace(0.0, 24.0 * np.pi, 24_001)).astype(np.float32)
+        p = Params(m=2, tau=2, eps=1.0, norm=2, theiler=1)
+    ref = oracle_lib.rqa(s, p)
+    for waves in (2, 8):
+        _announce("long_runs", case=case, waves=waves, n=len(s))
+        assert_same(run_gpu(s, p, cuda, waves=waves), *ref, tag=f"{case} waves {waves}")
