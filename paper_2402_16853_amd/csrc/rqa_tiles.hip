@@ -778,6 +778,84 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                 continue;
             }
 
+            if (interior && __ballot(X != ~0ull) == 0ull) {
+                // Every cell of an interior tile recurrent (dense series): the
+                // mirror image of the empty case.  Open white runs end at the
+                // tile's first cell, black runs grow by the cells they cross.
+                if constexpr (!FULL) {
+                    if (!hs.color) {
+                        finish_run<kHoriz>(hctx, 0u, hs.len, hs.first);
+                        hs = Run{1u, 64u, 0u};
+                    } else {
+                        hs.len += 64u;
+                    }
+                }
+                {
+                    Run st = wave == 0 ? Run{1u, 0u, 1u} : unpack_run(L.vs(slot, wave - 1, lane));
+                    const int64_t sidx = vbase + (jbase + lane);
+                    if (!st.color) {
+                        const LineCtx lc{&j, bins, sidx, true, 0u};
+                        finish_run<kVert>(lc, 0u, st.len, st.first);
+                        st = Run{1u, 64u, 0u};
+                    } else {
+                        st.len += 64u;
+                    }
+                    if (wave == nw - 1) {
+                        const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
+                        *glb(j.vlast + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;
+                    } else {
+                        L.vs(slot, wave, lane) = pack_run(st);
+                    }
+                }
+                {
+                    // Lane q's diagonal has 64 - q cells in the upper part and
+                    // q in the lower part (none for lane 0, whose lower run
+                    // passes through unchanged).
+                    const int kup = jbase + lane - R;
+                    const int klo = kup - 64;
+                    const uint32_t nup = 64u - (uint32_t)lane;
+                    Run up;
+                    if (wave == 0) {
+                        up = Run{1u, nup, 1u};   // black first run from the strip's top edge
+                    } else {
+                        up = unpack_run(L.ds(slot, wave - 1, lane));
+                        if (up.color) {
+                            up.len += nup;
+                        } else {
+                            if (up.first) {
+                                const LineCtx lc{&j, bins, dbase + kup, !FULL || dok(kup), 0u};
+                                finish_run<kDiag, kDW>(lc, 0u, up.len, 1u);
+                            }
+                            up = Run{1u, nup, 0u};
+                        }
+                    }
+                    Run lw = left;
+                    if (lane != 0) {
+                        if (lw.color) {
+                            lw.len += (uint32_t)lane;
+                        } else {
+                            if (lw.first) {
+                                const LineCtx lc{&j, bins, dbase + klo, !FULL || dok(klo), 0u};
+                                finish_run<kDiag, kDW>(lc, 0u, lw.len, 1u);
+                            }
+                            lw = Run{1u, (uint32_t)lane, 0u};
+                        }
+                    }
+                    if (wave < nw - 1) {
+                        L.ds(slot, wave, lane) = pack_run(lw);
+                    } else if (!FULL || dok(klo)) {
+                        const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
+                        *glb(j.dlast + dbase + klo) = b;
+                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
+                    }
+                    left = up;
+                }
+                if (wave > 0) publish_counter(&L.cons[wave - 1], t + 1);
+                if (wave < nw - 1) publish_counter(&L.prod[wave], t + 1);
+                continue;
+            }
+
             // ---- horizontal runs (row i of U) ----
             if constexpr (!FULL) {
                 if (lo_v < hi_v) {
