@@ -159,3 +159,37 @@ def test_given_matrix_of_a_cross_predicate(cuda, oracle_lib):
     for name in ("diag", "vert", "white"):
         assert np.array_equal(getattr(res_m, name), getattr(res_c, name)), name
     assert_same(res_c, *oracle_lib.cross_rqa(a, b, p), tag="cross")
+
+
+@pytest.mark.parametrize("w", [0, 3])
+def test_dense_full_matrices(w, cuda, oracle_lib):
+    """Fully recurrent interior tiles in the full-matrix modes: two constant
+    series (every cell recurrent), two slow sines (large recurrent blocks), and
+    a given matrix of large all-ones / all-zeros blocks."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    cases = [
+        (np.full(1500, 0.5), np.full(2300, 0.5), Params(m=2, tau=1, eps=0.0, norm=3, theiler=w)),
+        (np.sin(np.linspace(0, 6 * np.pi, 2600)), np.sin(np.linspace(0.5, 9 * np.pi, 3100)),
+         Params(m=2, tau=2, eps=1.0, norm=2, theiler=w)),
+    ]
+    for k, (a, b, p) in enumerate(cases):
+        for waves in (2, 8):
+            _announce("dense_cross", case=k, w=w, waves=waves, na=len(a), nb=len(b))
+            assert_same(gpu_cross(a, b, p, cuda, waves=waves),
+                        *oracle_lib.cross_rqa(a.astype(np.float32), b.astype(np.float32), p),
+                        tag=f"dense cross {k} w={w} waves {waves}")
+    nr, nc = 1500, 1100
+    ii, jj = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+    R = (((ii // 200) + (jj // 300)) % 2 == 0).astype(np.uint64)
+    bits = pack(R)
+    p = Params(m=1, tau=1, eps=0.0, norm=3, theiler=w)
+    ref_h = oracle_lib.matrix_histograms(bits, nr, nc, w)
+    ref_m = oracle_lib.rect_measures(*ref_h, nr, nc, w, p.lmin, p.vmin, p.wmin)
+    for waves in (2, 8):
+        _announce("dense_matrix", w=w, waves=waves)
+        comp = RQA.from_params(p)
+        comp.set_tiling(waves, 0)
+        res = comp.matrix(torch.from_numpy(bits.view(np.int64)).to(cuda), nc)
+        comp.close()
+        assert_same(res, ref_h, ref_m, tag=f"dense matrix w={w} waves {waves}")
