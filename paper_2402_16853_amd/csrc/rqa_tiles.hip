@@ -645,6 +645,14 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
     const int tfirst = cfirst - c0;              // first tile with cells for this wave
     if (wave > 0) publish_counter(&L.cons[wave - 1], wave_has_u ? tfirst : 0x7FFFFFFF);
     bool sync_ok = true;
+    // Given matrix: the next tile's row word is loaded while the current tile
+    // is processed (one load in flight per lane hides the memory latency that
+    // otherwise sets the pace of a strip).
+    const auto mrow = MODE == kModeMatrix && i < n ? glb(j.bits) + (int64_t)i * j.words : nullptr;
+    uint64_t mnext = 0;
+    if constexpr (MODE == kModeMatrix) {
+        if (mrow && wave_has_u && tfirst < T) mnext = mrow[c0 + tfirst];
+    }
     for (int t = wave_has_u ? tfirst : T; t < T; ++t) {
         const int c = c0 + t;
         const int slot = t & (kRing - 1);
@@ -652,7 +660,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
             const int jbase = c * 64;
             uint32_t xlo, xhi;
             if constexpr (MODE == kModeMatrix) {
-                const uint64_t word = i < n ? j.bits[(int64_t)i * j.words + c] : 0ull;
+                const uint64_t word = mnext;
+                if (mrow && t + 1 < T) mnext = mrow[c + 1];
                 xlo = (uint32_t)word;
                 xhi = (uint32_t)(word >> 32);
             } else {
