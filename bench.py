@@ -271,6 +271,14 @@ def bench_batched(args, torch, RQA, workload, windows_plan):
             comp.result_batch(w, histograms=False)
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
+    # one profiled run (hipEvents around each phase) for the tile kernel's rate
+    comp.set_profiling(True)
+    comp.run_batch(ds, off, ln)
+    comp.result_batch(0, histograms=False)
+    tm = comp.timings()
+    comp.set_profiling(False)
+    ops = sum(unique_pairs(int(v), p.theiler) for v in nv) * ops_per_pair(p.m, p.norm)
+    tile_tops = ops / (tm["tiles_ms"] * 1e-3) / 1e12
     # the same windows, one launch each
     single = RQA.from_params(p)
     views = [ds[int(o):int(o) + int(L)] for o, L in zip(off, ln)]
@@ -290,7 +298,9 @@ def bench_batched(args, torch, RQA, workload, windows_plan):
             "gcells_per_s": round(cells / tb / 1e9, 3),
             "sequential_ms": round(ts * 1e3, 3),
             "sequential_gcells_per_s": round(cells / ts / 1e9, 3),
-            "speedup_vs_sequential": round(ts / tb, 3)}
+            "speedup_vs_sequential": round(ts / tb, 3),
+            "tiles_ms": round(tm["tiles_ms"], 3), "stitch_ms": round(tm["stitch_ms"], 3),
+            "tile_tops": round(tile_tops, 3), "valu_frac": round(tile_tops / VALU_PEAK_TOPS, 4)}
 
 
 def bench_full_matrices(args, torch, RQA, workload):

@@ -1607,6 +1607,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
 
     std::vector<int> gkeys;
     int stitch_blocks = 0;
+    int stat_grid = 1;
     int ngroups = 0;
     int strip_acc = 0;
     for (int r = 0; r < njobs; ++r) {
@@ -1664,7 +1665,10 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         d.mins[0] = kp.lmin;
         d.mins[1] = kp.vmin;
         d.mins[2] = kp.wmin;
-        d.stat_blocks = (int32_t)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (hlen + 8191) / 8192));
+        // 2,048 lengths (8 per thread) per statistics block: the blocks' loops
+        // are chains of dependent loads, so short chains finish sooner.
+        d.stat_blocks = (int32_t)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (hlen + 2047) / 2048));
+        stat_grid = std::max(stat_grid, (int)d.stat_blocks);
         d.stats = reinterpret_cast<JobStats *>(reinterpret_cast<char *>(jb.flag) + 8);
         d.ent_part = reinterpret_cast<double *>(scr + lay.off_ent);
         strip_acc += lay.nstrips;
@@ -1725,8 +1729,8 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     if (phases) hipEventRecord(phases->ev[2], st);
     if (stitch_blocks > 0)
         hipLaunchKernelGGL(k_stitch, dim3(stitch_blocks), dim3(kStitchThreads), 0, st, ddesc, njobs);
-    hipLaunchKernelGGL(k_stats_moments, dim3(kStatMaxBlocks, njobs), dim3(kStatThreads), 0, st, ddesc);
-    hipLaunchKernelGGL(k_stats_entropy, dim3(kStatMaxBlocks, njobs), dim3(kStatThreads), 0, st, ddesc);
+    hipLaunchKernelGGL(k_stats_moments, dim3(stat_grid, njobs), dim3(kStatThreads), 0, st, ddesc);
+    hipLaunchKernelGGL(k_stats_entropy, dim3(stat_grid, njobs), dim3(kStatThreads), 0, st, ddesc);
     hipLaunchKernelGGL(k_stats_final, dim3((3 * njobs + 255) / 256), dim3(256), 0, st, ddesc, njobs);
     if (phases) hipEventRecord(phases->ev[3], st);
     return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
