@@ -89,7 +89,7 @@ constexpr int kCapW = 6016;    // LDS bins for white-vertical lengths < kCapW
 constexpr int kMaxM = 6;       // embedding dimensions held in registers
 constexpr int kRing = 4;       // carry slots per pair of consecutive waves (tiles in flight)
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls (~28 ms) before a neighbour wait gives up
-constexpr int kStitchThreads = 256;
+constexpr int kStitchThreads = 512;
 constexpr int kStitchBatch = 8;   // strips whose summaries a stitch thread loads at once
 constexpr int kStitchCapV = 2048; // stitch LDS bins for vertical lengths < kStitchCapV (the
                                   // stitch joins the runs that cross strip edges: long ones)
