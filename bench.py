@@ -254,21 +254,22 @@ def bench_batched(args, torch, RQA, workload, windows_plan):
     log(f"[bench] batched: {len(off)} windows, {cells:.3e} cells")
 
     def fetch_all():
-        for w in range(len(off)):
-            comp.result_batch(w, histograms=False)
+        # every window's measures in one library call
+        meas, status = comp.results_batch()
+        if status.any():
+            raise RuntimeError(f"batched windows failed: {np.unique(status).tolist()}")
+        return meas
 
     settle(comp, lambda: comp.run_batch(ds, off, ln), fetch_all)
     for _ in range(2):
         comp.run_batch(ds, off, ln)
-        for w in range(len(off)):
-            comp.result_batch(w, histograms=False)
+        fetch_all()
     reps = 3
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
         comp.run_batch(ds, off, ln)
-        for w in range(len(off)):
-            comp.result_batch(w, histograms=False)
+        fetch_all()
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / reps
     # one profiled run (hipEvents around each phase) for the tile kernel's rate

@@ -183,6 +183,15 @@ int rqa_run_batch(rqa_handle *h, const float *d_series, int64_t n_points,
 int rqa_result_batch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag,
                      uint64_t *vert, uint64_t *white, int64_t hist_len);
 
+/* The measures of every window of the last run in one call (waits for it):
+ * out[w] for w < count, with count equal to the number of windows (else
+ * RQA_ESIZE).  out and status (optional, may be NULL) are caller-owned host
+ * arrays of count entries.  status[w] is what rqa_result_batch returns for
+ * window w; a window without a result (e.g. RQA_ENONFINITE) gets NaN measures,
+ * n_rec 0 and its n_vec.  Returns RQA_OK, or the first window's error code.
+ * Same values as rqa_result_batch, without a call per window. */
+int rqa_result_batch_all(rqa_handle *h, rqa_measures *out, int32_t *status, int32_t count);
+
 /* Measures from host histograms of length n+1 (FP64, same definitions as
  * rqa_result). */
 int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert,

@@ -19,6 +19,7 @@ ERRORS = {
     -9: "RQA_EAGAIN", -10: "RQA_ENOTFOUND",
 }
 EAGAIN = -9
+ENONFINITE = -5
 
 
 class RqaParams(ctypes.Structure):
@@ -50,6 +51,7 @@ SIGNATURES = {
     "rqa_plot": (ctypes.c_int, [_P, _P, _I64, _P, _I64, _P]),
     "rqa_plot_cross": (ctypes.c_int, [_P, _P, _I64, _P, _I64, _P, _I64, _P]),
     "rqa_result_batch": (ctypes.c_int, [_P, _I32, ctypes.POINTER(RqaMeasures), _P, _P, _P, _I64]),
+    "rqa_result_batch_all": (ctypes.c_int, [_P, _P, _P, _I32]),
     "rqa_measures_from_hist": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(RqaParams),
                                               ctypes.POINTER(RqaMeasures)]),
     "rqa_set_tiling": (ctypes.c_int, [_P, _I32, _I32]),

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -652,6 +653,35 @@ int rqa_run_batch(rqa_handle *h, const float *d_series, int64_t n_points, const 
 int rqa_result_batch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag,
                      uint64_t *vert, uint64_t *white, int64_t hist_len) {
     return fetch(h, index, out, diag, vert, white, hist_len);
+}
+
+int rqa_result_batch_all(rqa_handle *h, rqa_measures *out, int32_t *status, int32_t count) {
+    if (!h || !out || count < 1) return RQA_EINVAL;
+    if (!h->has_run) return RQA_ESTATE;
+    if (count != static_cast<int32_t>(h->nvec.size())) return RQA_ESIZE;
+    int first = RQA_OK;
+    for (int32_t k = 0; k < count; ++k) {
+        const int rc = fetch(h, k, &out[k], nullptr, nullptr, nullptr, 0);
+        if (rc != RQA_OK) {
+            // No result for this window: NaN measures, nothing recurrent.
+            const double nan = std::numeric_limits<double>::quiet_NaN();
+            out[k] = rqa_measures{nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan,
+                                  0u, h->nvec[k]};
+            if (first == RQA_OK) first = rc;
+            // A device failure is not specific to one window: stop there.
+            if (rc == RQA_EDEVICE || rc == RQA_ENOMEM) {
+                for (int32_t r = k + 1; r < count; ++r) {
+                    out[r] = out[k];
+                    out[r].n_vec = h->nvec[r];
+                    if (status) status[r] = rc;
+                }
+                if (status) status[k] = rc;
+                return first;
+            }
+        }
+        if (status) status[k] = rc;
+    }
+    return first;
 }
 
 int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,

@@ -13,7 +13,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from ._lib import RqaMeasures, RqaParams, check, lib, EAGAIN, RQAError
+from ._lib import RQA_OK, ENONFINITE, RqaMeasures, RqaParams, check, lib, EAGAIN, RQAError
 
 NORMS = {"l1": 1, "taxicab": 1, "manhattan": 1, "l2": 2, "euclidean": 2,
          "linf": 3, "maximum": 3, "chebyshev": 3, 1: 1, 2: 2, 3: 3}
@@ -272,6 +272,21 @@ class RQA:
 
     def result_batch(self, index: int, histograms: bool = True) -> RQAResult:
         return self._fetch(int(index), histograms)
+
+    def results_batch(self):
+        """Measures of every window of the last run in one library call: a numpy
+        structured array (fields as rqa_measures) and the per-window status codes
+        (0 = OK; a window without a result has NaN measures)."""
+        count = len(self._hlen) if self._hlen else 0
+        if count < 1:
+            raise RuntimeError("rqa_result_batch_all: no run")
+        out = (RqaMeasures * count)()
+        status = np.zeros(count, dtype=np.int32)
+        rc = lib().rqa_result_batch_all(self._h, ctypes.cast(out, ctypes.c_void_p),
+                                        status.ctypes.data_as(ctypes.c_void_p), count)
+        if rc not in (RQA_OK, ENONFINITE):
+            check(rc, "rqa_result_batch_all")
+        return np.ctypeslib.as_array(out).copy(), status
 
     def _fetch(self, index, histograms):
         hl = self._hlen[0 if index is None else index] if self._hlen else 0

@@ -70,6 +70,10 @@ def test_handle_lifecycle_and_host_errors():
     assert L.rqa_result(h, ctypes.byref(ms), None, None, None, 0) == -7   # no run yet
     assert L.rqa_run(h, None, 100, None) == -1                   # null series
     assert L.rqa_run_batch(h, None, 100, None, None, 0, None) == -1
+    many = (RqaMeasures * 4)()
+    assert L.rqa_result_batch_all(h, ctypes.cast(many, ctypes.c_void_p), None, 4) == -7  # no run
+    assert L.rqa_result_batch_all(h, None, None, 4) == -1
+    assert L.rqa_result_batch_all(None, ctypes.cast(many, ctypes.c_void_p), None, 4) == -1
     assert L.rqa_set_tiling(h, 9, 0) == -1
     assert L.rqa_set_tiling(h, 4, 0) == 0
     L.rqa_destroy(h)
