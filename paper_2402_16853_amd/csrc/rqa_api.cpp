@@ -668,16 +668,6 @@ int rqa_result_batch_all(rqa_handle *h, rqa_measures *out, int32_t *status, int3
             out[k] = rqa_measures{nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan,
                                   0u, h->nvec[k]};
             if (first == RQA_OK) first = rc;
-            // A device failure is not specific to one window: stop there.
-            if (rc == RQA_EDEVICE || rc == RQA_ENOMEM) {
-                for (int32_t r = k + 1; r < count; ++r) {
-                    out[r] = out[k];
-                    out[r].n_vec = h->nvec[r];
-                    if (status) status[r] = rc;
-                }
-                if (status) status[k] = rc;
-                return first;
-            }
         }
         if (status) status[k] = rc;
     }
