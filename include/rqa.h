@@ -183,7 +183,8 @@ int rqa_run_batch(rqa_handle *h, const float *d_series, int64_t n_points,
 int rqa_result_batch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *diag,
                      uint64_t *vert, uint64_t *white, int64_t hist_len);
 
-/* The measures of every window of the last run in one call (waits for it):
+/* The measures of every window of the last run in one call (waits for it;
+ * the per-window quantities of Sect. 2, for the windows of Sect. 3's epochs):
  * out[w] for w < count, with count equal to the number of windows (else
  * RQA_ESIZE).  out and status (optional, may be NULL) are caller-owned host
  * arrays of count entries.  status[w] is what rqa_result_batch returns for
