@@ -189,7 +189,8 @@ int rqa_result_batch(rqa_handle *h, int32_t index, rqa_measures *out, uint64_t *
  * RQA_ESIZE).  out and status (optional, may be NULL) are caller-owned host
  * arrays of count entries.  status[w] is what rqa_result_batch returns for
  * window w; a window without a result (e.g. RQA_ENONFINITE) gets NaN measures,
- * n_rec 0 and its n_vec.  Returns RQA_OK, or the first window's error code.
+ * n_rec 0 and its n_vec.  Returns RQA_OK, or the code of the first window that
+ * has no result.
  * Same values as rqa_result_batch, without a call per window. */
 int rqa_result_batch_all(rqa_handle *h, rqa_measures *out, int32_t *status, int32_t count);
 
