@@ -475,20 +475,31 @@ static double oracle_longest(const uint64_t *h, int64_t n)
 }
 
 /* Shannon entropy (natural log) of the line-length distribution over l >= from,
- * normalised by the number of such lines; empty classes are skipped. */
+ * normalised by the number of such lines; empty classes are skipped.  The
+ * paper fixes no summation order, so the terms -p ln p are added in ascending l
+ * with Neumaier's compensated summation (the improved Kahan-Babuska sum): the
+ * result is the sum of the computed terms to within a few ulps however many
+ * classes there are (a plain running sum drifts by ~1e-11 relative over the
+ * ~2.3e5 classes of a long, almost periodic series). */
 static double oracle_entropy(const uint64_t *h, int64_t n, int64_t from)
 {
-    double total = oracle_sum(h, n, from, 0), acc = 0.0;
+    double total = oracle_sum(h, n, from, 0), sum = 0.0, comp = 0.0;
     int64_t l;
     if (total == 0.0)
         return NAN;
     for (l = from < 1 ? 1 : from; l <= n; ++l) {
         if (h[l] > 0) {
             double p = (double)h[l] / total;
-            acc -= p * log(p);
+            double term = -(p * log(p));
+            double t = sum + term;
+            if (fabs(sum) >= fabs(term))
+                comp += (sum - t) + term;
+            else
+                comp += (term - t) + sum;
+            sum = t;
         }
     }
-    return acc;
+    return sum + comp;
 }
 
 /* Measures from histograms of `n` entries past index 0 over `cells` matrix

@@ -20,15 +20,23 @@ struct Moments {
 };
 
 // Shannon entropy (natural log) of the distribution of lines of length >= floor.
+// A long histogram has ~10^5 classes, over which a running sum loses ~1e-11
+// relative; the terms are summed as Ogita-Rump-Oishi "Sum2" (Knuth's
+// error-free TwoSum per addition, the rounding errors accumulated apart and
+// added at the end), which is as accurate as summing in twice the precision.
 double entropy(const uint64_t *h, int64_t n, int64_t floor_len, double count) {
     if (count == 0.0) return std::numeric_limits<double>::quiet_NaN();
-    double e = 0.0;
+    double s = 0.0, err = 0.0;
     for (int64_t l = floor_len < 1 ? 1 : floor_len; l <= n; ++l) {
         if (h[l] == 0) continue;
         const double p = static_cast<double>(h[l]) / count;
-        e -= p * std::log(p);
+        const double x = -(p * std::log(p));
+        const double t = s + x;
+        const double z = t - s;
+        err += (s - (t - z)) + (x - z);
+        s = t;
     }
-    return e;
+    return s + err;
 }
 
 double ratio(double a, double b) {

@@ -3,6 +3,9 @@ recompute in every test run.  Calls only the CPU oracle (oracle/) and the
 seeded generators (workloads/); nothing here touches the HIP path.
 
     python tests/golden/make_golden.py lorenz 0        # ~10-20 min on 8 cores
+    python tests/golden/make_golden.py sine 0          # the paper's 1,000,001-point sine
+    python tests/golden/make_golden.py lorenz 0 --measures-only
+                                    # recompute the measures from the stored histograms
 """
 import json
 import os
@@ -42,5 +45,29 @@ def main(name, seed):
     print(path, f"{dt:.1f}s")
 
 
+def refresh_measures(name, seed):
+    """Recompute the stored measures from the stored histograms (after a change
+    to the oracle's measure arithmetic; the histograms stay as written)."""
+    path = os.path.join(HERE, f"{name}_seed{seed}.json")
+    g = json.load(open(path))
+    n = g["n_vec"]
+    dense = []
+    for key in ("diag", "vert", "white"):
+        h = np.zeros(n + 1, dtype=np.uint64)
+        for k, v in g[key].items():
+            h[int(k)] = v
+        dense.append(h)
+    p = g["params"]
+    meas = oracle.measures(*dense, p["theiler"], p["lmin"], p["vmin"], p["wmin"])
+    g["measures"] = {k: (None if not np.isfinite(x) else x) for k, x in meas.items()}
+    with open(path, "w") as f:
+        json.dump(g, f)
+    print(path, "measures refreshed")
+
+
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 0)
+    if "--measures-only" in sys.argv:
+        args = [a for a in sys.argv[1:] if a != "--measures-only"]
+        refresh_measures(args[0], int(args[1]) if len(args) > 1 else 0)
+    else:
+        main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 0)

@@ -75,3 +75,38 @@ def test_library_matches_oracle_measures(name, seed, theiler):
     got = measures_from_hist(d, v, w, p)
     for k, r in ref.items():
         assert close(got[k], r), (k, got[k], r)
+
+
+def _exact_entropy(h, floor):
+    """The entropy with its terms summed exactly (math.fsum, Shewchuk's exact
+    summation): an independent value for the long-histogram case."""
+    ls = [l for l in range(max(floor, 1), len(h)) if h[l]]
+    total = float(sum(int(h[l]) for l in ls))
+    terms = [-(float(h[l]) / total) * math.log(float(h[l]) / total) for l in ls]
+    return math.fsum(terms)
+
+
+@pytest.mark.parametrize("classes", [2_000, 250_000])
+def test_entropy_of_long_histograms(classes):
+    """A histogram with ~10^5 occupied lengths (as a long, almost periodic
+    series produces): both implementations give the entropy within a few ulps
+    of the exactly summed value.  A plain running sum is ~1e-11 off here, which
+    this bound rejects."""
+    from paper_2402_16853_amd import measures_from_hist
+    rng = np.random.default_rng(classes)
+    n = classes + 10
+    h = np.zeros(n + 1, dtype=np.uint64)
+    h[2:classes + 2] = (rng.pareto(1.5, size=classes) * 50 + 1).astype(np.uint64)
+    ref = _exact_entropy(h, 2)
+    z = np.zeros(n + 1, dtype=np.uint64)
+    p = Params(m=1, tau=1, eps=0.1, norm=2, lmin=2, vmin=2, wmin=2, theiler=1)
+    for got in (oracle.measures(h, z, z, 1, 2, 2, 2)["l_entr"],
+                measures_from_hist(h, z, z, p)["l_entr"]):
+        assert abs(got - ref) <= 8 * np.spacing(ref), (got, ref)
+    naive = 0.0
+    tot = float(h[2:].sum())
+    for c in h[2:]:
+        if c:
+            naive -= (float(c) / tot) * math.log(float(c) / tot)
+    if classes > 100_000:
+        assert abs(naive - ref) > 8 * np.spacing(ref)   # the case the bound is for
