@@ -1,8 +1,13 @@
-"""Full-size parity (GPU): the Lorenz-63 headline workload (N = 1,048,576,
-m=3, tau=10, L-infinity, eps = 0.05 std, Theiler 1) in the launch configuration
-the benchmark times, against oracle histograms stored in tests/golden/ (written
-by tests/golden/make_golden.py, which calls only the CPU oracle; about 16 min on
-8 cores, too slow to recompute per run)."""
+"""Full-size parity (GPU) in the launch configuration the benchmark times,
+against oracle histograms stored in tests/golden/ (written by
+tests/golden/make_golden.py, which calls only the CPU oracle; 15-30 min each on
+8 cores, too slow to recompute per run):
+
+* the Lorenz-63 headline workload (N = 1,048,576, m=3, tau=10, L-infinity,
+  eps = 0.05 std, Theiler 1);
+* the paper's runtime workload, a sine of 1,000,001 points (m=2, tau=2, L2,
+  eps=1.0, Theiler 1), whose recurrence rate is about one half: most runs are
+  hundreds of cells long and cross strip edges."""
 import hashlib
 import json
 import os
@@ -14,7 +19,7 @@ from workloads import workload
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lorenz_seed0.json")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def dense(sparse, n):
@@ -24,23 +29,24 @@ def dense(sparse, n):
     return h
 
 
-def test_lorenz_full_size_bit_exact(cuda):
+@pytest.mark.parametrize("name", ["lorenz", "sine"])
+def test_full_size_bit_exact(name, cuda):
     import torch
     from paper_2402_16853_amd import RQA
-    g = json.load(open(GOLDEN))
-    s, p = workload("lorenz", seed=g["seed"])
+    g = json.load(open(os.path.join(GOLDEN_DIR, f"{name}_seed0.json")))
+    s, p = workload(name, seed=g["seed"])
     assert hashlib.sha256(s.tobytes()).hexdigest()[:16] == g["series_sha_prefix"], \
         "generator output changed; regenerate the golden"
     assert p.asdict() == g["params"]
     n = g["n_vec"]
-    print(f"[case] lorenz full size n_vec={n}", flush=True)
+    print(f"[case] {name} full size n_vec={n}", flush=True)
     comp = RQA.from_params(p)
     res = comp(torch.from_numpy(s).to(cuda))
     comp.close()
-    for name in ("diag", "vert", "white"):
-        ref = dense(g[name], n)
-        got = getattr(res, name)
-        assert np.array_equal(got, ref), f"{name} differs at {np.nonzero(got != ref)[0][:8]}"
+    for h in ("diag", "vert", "white"):
+        ref = dense(g[h], n)
+        got = getattr(res, h)
+        assert np.array_equal(got, ref), f"{name} {h} differs at {np.nonzero(got != ref)[0][:8]}"
     for k, ref in g["measures"].items():
         got = res.measures[k]
         if ref is None:
