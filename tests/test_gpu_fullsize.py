@@ -7,7 +7,9 @@ tests/golden/make_golden.py, which calls only the CPU oracle; 15-30 min each on
   eps = 0.05 std, Theiler 1);
 * the paper's runtime workload, a sine of 1,000,001 points (m=2, tau=2, L2,
   eps=1.0, Theiler 1), whose recurrence rate is about one half: most runs are
-  hundreds of cells long and cross strip edges."""
+  hundreds of cells long and cross strip edges;
+* the cross recurrence of two Lorenz-63 trajectories of 262,144 points each
+  (the benchmark's full-matrix workload)."""
 import hashlib
 import json
 import os
@@ -47,6 +49,36 @@ def test_full_size_bit_exact(name, cuda):
         ref = dense(g[h], n)
         got = getattr(res, h)
         assert np.array_equal(got, ref), f"{name} {h} differs at {np.nonzero(got != ref)[0][:8]}"
+    for k, ref in g["measures"].items():
+        got = res.measures[k]
+        if ref is None:
+            assert np.isnan(got), k
+        else:
+            assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (k, got, ref)
+
+
+def test_cross_full_size_bit_exact(cuda):
+    """Cross recurrence of two Lorenz-63 trajectories of 262,144 points each
+    (6.9e10 cells, every one evaluated), as the benchmark runs it."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    g = json.load(open(os.path.join(GOLDEN_DIR, "lorenz_cross_seed1_2.json")))
+    a, p = workload("lorenz", seed=g["seeds"][0], n=g["n_points"])
+    b, _ = workload("lorenz", seed=g["seeds"][1], n=g["n_points"])
+    for x, want in zip((a, b), g["series_sha_prefix"]):
+        assert hashlib.sha256(x.tobytes()).hexdigest()[:16] == want, \
+            "generator output changed; regenerate the golden"
+    assert p.asdict() == g["params"]
+    print(f"[case] lorenz cross full size n_points={g['n_points']}", flush=True)
+    comp = RQA.from_params(p)
+    res = comp.cross(torch.from_numpy(a).to(cuda), torch.from_numpy(b).to(cuda))
+    comp.close()
+    hl = g["hist_len"]
+    for h in ("diag", "vert", "white"):
+        ref = dense(g[h], hl - 1)
+        got = getattr(res, h)
+        assert got.shape == ref.shape, (h, got.shape, ref.shape)
+        assert np.array_equal(got, ref), f"cross {h} differs at {np.nonzero(got != ref)[0][:8]}"
     for k, ref in g["measures"].items():
         got = res.measures[k]
         if ref is None:
