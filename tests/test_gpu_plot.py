@@ -82,3 +82,26 @@ def test_plot_words_and_errors(cuda):
     assert lib().rqa_plot(comp._h, ctypes.c_void_p(dev(s, cuda).data_ptr()), 300,
                           ctypes.c_void_p(small.data_ptr()), 4, None) == -6
     comp.close()
+
+
+def test_plot_and_matrix_at_benchmark_size(cuda, oracle_lib):
+    """The benchmark's plot and given-matrix workload: the packed plot of the
+    first 65,536 points of a 262,144-point Lorenz-63 series (its embedding and
+    radius), then the RQA of that plot as a given matrix, against the oracle's
+    RQA of the same points (histograms bit-exact, measures within 1e-12)."""
+    from paper_2402_16853_amd import RQA
+    a, p = workload("lorenz", seed=1, n=262_144)
+    s = np.ascontiguousarray(a[:65_536])
+    n = len(s) - (p.m - 1) * p.tau
+    _announce("plot_matrix_65536", n=n)
+    comp = RQA.from_params(p)
+    bits = comp.plot(dev(s, cuda))
+    via = comp.matrix(bits, n)
+    comp.close()
+    (d, v, w), meas = oracle_lib.rqa(s, p)
+    for name, ref in (("diag", d), ("vert", v), ("white", w)):
+        got = getattr(via, name)
+        assert np.array_equal(got, ref), f"{name} differs at {np.nonzero(got != ref)[0][:8]}"
+    for k, ref in meas.items():
+        got = via.measures[k]
+        assert (np.isnan(ref) and np.isnan(got)) or abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), k
