@@ -1491,6 +1491,14 @@ struct Layout {
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Offset of the first evaluated diagonal of U, max(theiler, 1), clamped to n:
+// every window of n or more masks the whole matrix alike, and the clamp keeps
+// the kernels' 32-bit row + offset arithmetic from overflowing.
+int effective_wp(int32_t theiler, int64_t n) {
+    const int64_t w = theiler > 1 ? theiler : 1;
+    return (int)(w < n ? w : (n > 1 ? n : 1));
+}
+
 int default_waves_impl(int64_t n) {
     // Eight waves per workgroup (two workgroups per compute unit) measured
     // fastest for long series; short series use four so that more strips exist.
@@ -1501,7 +1509,7 @@ int default_waves_impl(int64_t n) {
 Layout layout_of(const Job &jb) {
     Layout L{};
     const int64_t n = jb.n_vec;
-    const int wp = jb.kp.theiler > 1 ? jb.kp.theiler : 1;
+    const int wp = effective_wp(jb.kp.theiler, n);
     L.H = 64 * (jb.waves > 0 ? jb.waves : default_waves_impl(n));
     if (jb.mode == kModeAuto) {
         L.nstrips = n - wp > 0 ? (int)((n - wp + L.H - 1) / L.H) : 0;
@@ -1653,7 +1661,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         d.tau = kp.tau;
         d.norm = kp.norm;
         d.theiler = kp.theiler;
-        d.wp = kp.theiler > 1 ? kp.theiler : 1;
+        d.wp = effective_wp(kp.theiler, jb.n_vec);
         d.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
         d.thr0 = kp.d0_bound;
         d.H = lay.H;

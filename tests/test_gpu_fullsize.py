@@ -1,5 +1,6 @@
-"""Full-size parity (GPU) in the launch configuration the benchmark times,
-against oracle histograms stored in tests/golden/ (written by
+"""Full-size parity (GPU) in the launch configurations the benchmark times
+(every workgroup shape the autotuner may pick: 8, 4 and 2 waves; the bench
+settles on 8 at these sizes), against oracle histograms stored in tests/golden/ (written by
 tests/golden/make_golden.py, which calls only the CPU oracle; 15-30 min each on
 8 cores, too slow to recompute per run):
 
@@ -9,7 +10,9 @@ tests/golden/make_golden.py, which calls only the CPU oracle; 15-30 min each on
   eps=1.0, Theiler 1), whose recurrence rate is about one half: most runs are
   hundreds of cells long and cross strip edges;
 * the cross recurrence of two Lorenz-63 trajectories of 262,144 points each
-  (the benchmark's full-matrix workload)."""
+  (the benchmark's full-matrix workload);
+* the sine again with the line of identity kept (Theiler 0), stored as digests
+  of the dense histograms."""
 import hashlib
 import json
 import os
@@ -22,6 +25,19 @@ from workloads import workload
 pytestmark = pytest.mark.gpu
 
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# Workgroup shapes (waves per workgroup) the autotuner chooses among.
+TUNER_SHAPES = (8, 4, 2)
+
+
+def check_measures(res, ref_measures):
+    for k, ref in ref_measures.items():
+        got = res.measures[k]
+        if ref is None:
+            assert np.isnan(got), k
+        else:
+            assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (k, got, ref)
 
 
 def dense(sparse, n):
@@ -41,20 +57,20 @@ def test_full_size_bit_exact(name, cuda):
         "generator output changed; regenerate the golden"
     assert p.asdict() == g["params"]
     n = g["n_vec"]
-    print(f"[case] {name} full size n_vec={n}", flush=True)
     comp = RQA.from_params(p)
-    res = comp(torch.from_numpy(s).to(cuda))
+    ds = torch.from_numpy(s).to(cuda)
+    refs = {h: dense(g[h], n) for h in ("diag", "vert", "white")}
+    for waves in TUNER_SHAPES:
+        print(f"[case] {name} full size n_vec={n} waves={waves}", flush=True)
+        comp.set_tiling(waves, 0)
+        res = comp(ds)
+        assert comp.last_launch()["waves"] == waves
+        for h in ("diag", "vert", "white"):
+            got = getattr(res, h)
+            assert np.array_equal(got, refs[h]), \
+                f"{name} waves {waves} {h} differs at {np.nonzero(got != refs[h])[0][:8]}"
+        check_measures(res, g["measures"])
     comp.close()
-    for h in ("diag", "vert", "white"):
-        ref = dense(g[h], n)
-        got = getattr(res, h)
-        assert np.array_equal(got, ref), f"{name} {h} differs at {np.nonzero(got != ref)[0][:8]}"
-    for k, ref in g["measures"].items():
-        got = res.measures[k]
-        if ref is None:
-            assert np.isnan(got), k
-        else:
-            assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (k, got, ref)
 
 
 def test_cross_full_size_bit_exact(cuda):
@@ -69,19 +85,39 @@ def test_cross_full_size_bit_exact(cuda):
         assert hashlib.sha256(x.tobytes()).hexdigest()[:16] == want, \
             "generator output changed; regenerate the golden"
     assert p.asdict() == g["params"]
-    print(f"[case] lorenz cross full size n_points={g['n_points']}", flush=True)
     comp = RQA.from_params(p)
-    res = comp.cross(torch.from_numpy(a).to(cuda), torch.from_numpy(b).to(cuda))
-    comp.close()
+    da, db = torch.from_numpy(a).to(cuda), torch.from_numpy(b).to(cuda)
     hl = g["hist_len"]
-    for h in ("diag", "vert", "white"):
-        ref = dense(g[h], hl - 1)
-        got = getattr(res, h)
-        assert got.shape == ref.shape, (h, got.shape, ref.shape)
-        assert np.array_equal(got, ref), f"cross {h} differs at {np.nonzero(got != ref)[0][:8]}"
-    for k, ref in g["measures"].items():
-        got = res.measures[k]
-        if ref is None:
-            assert np.isnan(got), k
-        else:
-            assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (k, got, ref)
+    for waves in TUNER_SHAPES:
+        print(f"[case] lorenz cross full size n_points={g['n_points']} waves={waves}", flush=True)
+        comp.set_tiling(waves, 0)
+        res = comp.cross(da, db)
+        for h in ("diag", "vert", "white"):
+            ref = dense(g[h], hl - 1)
+            got = getattr(res, h)
+            assert got.shape == ref.shape, (h, got.shape, ref.shape)
+            assert np.array_equal(got, ref), \
+                f"cross waves {waves} {h} differs at {np.nonzero(got != ref)[0][:8]}"
+        check_measures(res, g["measures"])
+    comp.close()
+
+
+def test_sine_with_line_of_identity(cuda):
+    """The paper's runtime workload with the line of identity kept (Theiler 0),
+    as the benchmark also times it: histograms equal the oracle's (digests of
+    the dense arrays), measures within 1e-12."""
+    import torch
+    from golden_digest import check_record
+    from paper_2402_16853_amd import RQA
+    g = json.load(open(os.path.join(GOLDEN_DIR, "sine_w0_digest.json")))
+    s, p = workload("sine")
+    assert hashlib.sha256(s.tobytes()).hexdigest()[:16] == g["series_sha_prefix"]
+    p = type(p)(**{**p.asdict(), "theiler": 0})
+    assert p.asdict() == g["params"]
+    comp = RQA.from_params(p)
+    ds = torch.from_numpy(s).to(cuda)
+    for waves in TUNER_SHAPES:
+        print(f"[case] sine theiler 0 full size waves={waves}", flush=True)
+        comp.set_tiling(waves, 0)
+        check_record(comp(ds), g, f"sine w=0 waves {waves}")
+    comp.close()

@@ -165,3 +165,19 @@ def test_long_runs_across_strips(case, cuda, oracle_lib):
     for waves in (2, 8):
         _announce("long_runs", case=case, waves=waves, n=len(s))
         assert_same(run_gpu(s, p, cuda, waves=waves), *ref, tag=f"{case} waves {waves}")
+
+
+@pytest.mark.parametrize("theiler", ["n-1", "n", "n+1", "2^31-1"])
+def test_theiler_at_and_beyond_n(theiler, cuda, oracle_lib):
+    """Theiler windows that mask all but a corner of the matrix, all of it, or
+    reach the top of the 32-bit range: the window is clamped to n before any
+    row + window sum is formed on the device, with the same results."""
+    rng = np.random.default_rng(8)
+    s = (np.cumsum(rng.normal(size=700)) * 0.05).astype(np.float32)
+    n = len(s) - 2
+    w = {"n-1": n - 1, "n": n, "n+1": n + 1, "2^31-1": 2**31 - 1}[theiler]
+    p = Params(m=2, tau=2, eps=5.0, norm=3, theiler=w)
+    ref = oracle_lib.rqa(s, p)
+    for waves in (1, 8):
+        _announce("theiler_large", theiler=w, n=n, waves=waves)
+        assert_same(run_gpu(s, p, cuda, waves=waves), *ref, tag=f"theiler {w} waves {waves}")

@@ -116,3 +116,40 @@ def test_poll_before_done_and_nonfinite(cuda):
     with pytest.raises(RQAError):
         srv.wait(t2)
     srv.close()
+
+
+def test_served_stream_largest_jobs_match_oracle(cuda, oracle_lib):
+    """The 16 longest jobs among the first 400 requests of the served benchmark
+    stream (up to 2e5 points each, mixed m, tau, norm; eps at RR ~ 5%), served
+    in a mix with the stream's short jobs: each equals the oracle (digests of
+    its dense histograms stored by tests/golden/make_golden.py, which calls only
+    the oracle), and the short ones equal the oracle computed here."""
+    import json
+    import os
+
+    import torch
+    from golden_digest import check_record
+    from paper_2402_16853_amd import Server
+    g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "served_large_seed0_digest.json")))
+    reqs = served_requests(g["count"], rate_hz=g["rate_hz"], seed=g["seed"])
+    big = {rec["request"]: rec for rec in g["jobs"]}
+    small = [k for k in range(g["count"]) if len(reqs[k].series) <= 3000][:48]
+    order = sorted(list(big) + small)
+    dser = {k: torch.from_numpy(reqs[k].series).to(cuda) for k in order}
+    torch.cuda.synchronize()
+    srv = Server(16 << 30, streams=4)
+    _announce("serve-stream-largest", large=len(big), small=len(small))
+    tickets = {k: srv.submit(reqs[k].params, dser[k]) for k in order}
+    served = {k: srv.wait(t) for k, t in tickets.items()}
+    srv.close()
+    for k in order:
+        r = reqs[k]
+        if k in big:
+            assert r.params.asdict() == big[k]["params"]
+            check_record(served[k], big[k], f"request {k} n={len(r.series)}")
+        else:
+            ref = oracle_lib.histograms(r.series, r.params.m, r.params.tau, r.params.eps,
+                                        r.params.norm, r.params.theiler)
+            got = served[k]
+            assert all(np.array_equal(x, y) for x, y in zip((got.diag, got.vert, got.white), ref)), k

@@ -139,3 +139,31 @@ def test_plot_histograms_match_line_oracles():
                 oracle.histograms(s, 3, 2, 0.2, 2, 2))
     assert same(oracle.matrix_histograms(oracle.plot(s, p, b), n, nb, 0),
                 oracle.cross_histograms(s, b, 3, 2, 0.2, 2, 2))
+
+
+@pytest.mark.parametrize("na,nb,w", [(7, 4, 1), (4, 7, 2), (30, 11, 5), (11, 30, 5), (9, 40, 9),
+                                     (40, 9, 10), (13, 6, 7), (6, 13, 20), (25, 25, 3),
+                                     (1, 17, 1), (17, 1, 2), (50, 23, 23)])
+def test_rect_rr_denominator_brute_force(na, nb, w):
+    """The RR denominator of a rectangular matrix with a Theiler band (the cells
+    with |i-j| >= w, Sect. 3 reading of the band for cross recurrence), counted
+    cell by cell: RR equals N_rec over that count, for unequal shapes, bands
+    wider than the shorter side and bands that cover everything."""
+    rng = np.random.default_rng(na * 1000 + nb * 10 + w)
+    a = rng.random(na).astype(np.float32)
+    b = rng.random(nb).astype(np.float32)
+    R = brute.cross_matrix(a, b, 1, 1, 0.4, 3, w)
+    n_rec = sum(sum(row) for row in R)
+    outside = sum(1 for i in range(na) for j in range(nb) if abs(i - j) >= w)
+    hists = oracle.cross_histograms(a, b, 1, 1, 0.4, 3, w)
+    ms = oracle.rect_measures(*hists, na, nb, w, 2, 2, 2)
+    assert ms["n_rec"] == n_rec
+    if outside == 0:
+        assert np.isnan(ms["rr"])
+    else:
+        assert ms["rr"] == n_rec / outside, (ms["rr"], n_rec, outside)
+    # all-ones rectangle: every cell outside the band is recurrent, RR = 1
+    c = oracle.cross_histograms(np.zeros(na, np.float32), np.zeros(nb, np.float32), 1, 1, 0.0, 3, w)
+    mc = oracle.rect_measures(*c, na, nb, w, 2, 2, 2)
+    assert mc["n_rec"] == outside
+    assert (np.isnan(mc["rr"]) if outside == 0 else mc["rr"] == 1.0)
