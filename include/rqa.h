@@ -53,7 +53,8 @@ extern "C" {
 #define RQA_ENONFINITE (-5)  /* the series holds NaN or +-Inf (detected on device)   */
 #define RQA_ESIZE (-6)       /* a caller buffer is shorter than required             */
 #define RQA_ESTATE (-7)      /* call order violated (e.g. result before run)         */
-#define RQA_EBUDGET (-8)     /* a job needs more device memory than the server owns  */
+#define RQA_EBUDGET (-8)     /* a job needs more device memory than the server owns
+                                or than rqa_run_static's scratch holds             */
 #define RQA_EAGAIN (-9)      /* a served job is not finished yet                     */
 #define RQA_ENOTFOUND (-10)  /* unknown ticket                                       */
 
@@ -221,6 +222,33 @@ int rqa_get_timings(rqa_handle *h, double *prepare_ms, double *tiles_ms, double 
  * hipGraph (identical repeated launches are captured once and replayed).
  * RQA_ESTATE before the first run. */
 int rqa_last_launch(const rqa_handle *h, int32_t *waves, int32_t *graph_replay);
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * RQA as rqa_run + rqa_result of one device series under the parameters *p,
+ * enqueued on hip_stream with no allocation at all (no hipMalloc, hipFree,
+ * pinned host buffer or host-to-device copy): the kernels' scratch lies in a
+ * static device array of RQA_STATIC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends.  That limit admits series of up
+ * to about 92,000 delay vectors; a larger one returns RQA_EBUDGET.
+ *   d_series: n_points FP32 values in device memory (caller-owned, alive and
+ *             unmodified until the stream has passed the call);
+ *   d_hist:   caller-owned DEVICE array of 3*hist_len uint64, hist_len >= n+1
+ *             (else RQA_ESIZE): diag at [0, hist_len), vert at [hist_len,
+ *             2 hist_len), white at [2 hist_len, 3 hist_len); entries 0..n of
+ *             each are written, the rest are left unchanged;
+ *   d_flag:   caller-owned DEVICE int32, written 0 when the run is valid; bit 0
+ *             set means the series holds NaN or +-Inf (rqa_result's
+ *             RQA_ENONFINITE), any other bit an internal device error.
+ * Measures follow from the histograms copied to the host with
+ * rqa_measures_from_hist.  Host-detectable errors (RQA_EINVAL, RQA_ETOOSHORT,
+ * RQA_ESIZE, RQA_EBUDGET) return before anything is enqueued.  All calls on one
+ * GPU share its scratch array, which keeps the last call's contents: calls
+ * whose work overlaps on one GPU (other streams, other threads) race, so
+ * serialise them, e.g. on one stream. */
+#define RQA_STATIC_SCRATCH_BYTES (64u << 20)
+int rqa_run_static(const rqa_params *p, const float *d_series, int64_t n_points,
+                   uint64_t *d_hist, int64_t hist_len, int32_t *d_flag, void *hip_stream);
 
 /* Release the handle and its device workspace (waits for outstanding work). */
 void rqa_destroy(rqa_handle *h);

@@ -72,6 +72,7 @@ SIGNATURES = {
     "rqa_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(RqaMeasures), _P, _P, _P,
                                 _I64]),
     "rqa_server_destroy": (None, [_P]),
+    "rqa_run_static": (ctypes.c_int, [ctypes.POINTER(RqaParams), _P, _I64, _P, _I64, _P, _P]),
 }
 
 _lib = None

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(REPO, "include")
 LIB = os.path.join(HERE, "librqa.so")
 
-SOURCES = ["rqa_tiles.hip", "rqa_api.cpp", "rqa_measures.cpp", "rqa_server.cpp"]
+SOURCES = ["rqa_tiles.hip", "rqa_api.cpp", "rqa_measures.cpp", "rqa_server.cpp",
+           "rqa_static.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("RQA_OFFLOAD_ARCH", "gfx950")

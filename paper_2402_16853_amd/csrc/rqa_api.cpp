@@ -749,7 +749,7 @@ const char *rqa_strerror(int code) {
         case RQA_ENONFINITE: return "series contains NaN or infinity";
         case RQA_ESIZE: return "output buffer too small";
         case RQA_ESTATE: return "invalid call order";
-        case RQA_EBUDGET: return "job exceeds the server memory budget";
+        case RQA_EBUDGET: return "job exceeds the memory budget (server pool or static scratch)";
         case RQA_EAGAIN: return "job not finished";
         case RQA_ENOTFOUND: return "unknown ticket";
         default: return "unknown error";

@@ -65,6 +65,8 @@ struct Job {
     uint64_t *hist = nullptr;       // device: 3*hist_len() u64 -- diag | vert | white
     int *flag = nullptr;            // device info record (kInfoBytes): flag at 0, JobStats at 8
     void *scratch = nullptr;        // device: engine_job_scratch_bytes(*this) bytes
+    void *stats = nullptr;          // device JobStats record (nullptr: at flag + 8)
+    int64_t hist_stride = 0;        // entries from one histogram to the next (0: hist_len())
     KParams kp{};                   // parameters of this job
     int waves = 0;                  // waves per workgroup (strip height 64*waves), > 0
     // Histogram entries (index = line length, 0 unused): longest line + 1.
@@ -121,6 +123,14 @@ struct AuxStreams {
 int engine_launch(const std::vector<Job> &jobs, void *launch_scratch, void *staging,
                   hipEvent_t staging_free, int groups, hipStream_t stream,
                   const PhaseEvents *phases = nullptr, AuxStreams *aux = nullptr);
+
+// The launch of one job (auto mode) without host staging: descriptors are
+// written by a kernel from its arguments and every scratch byte lies in
+// `scratch` (engine_static_bytes(jb) device bytes): the job's histograms
+// (jb.hist, stride jb.hist_stride) and flag (jb.flag) are the caller's.  No
+// allocation, no host-to-device copy.
+size_t engine_static_bytes(const Job &jb);
+int engine_launch_static(Job jb, void *scratch, hipStream_t stream);
 
 // Recurrence plot: the masked matrix of series a (b == nullptr) or the cross
 // matrix of a and b, bit-packed into `bits` (rows of `words` u64), on `stream`.

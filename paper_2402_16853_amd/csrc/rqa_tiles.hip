@@ -530,6 +530,15 @@ __global__ void k_reset(const JobDesc *__restrict__ jobs, int njobs, int *counte
     if (t < ncounters) counters[t] = 0;
 }
 
+// Write the descriptors of a one-job launch from kernel arguments (the launch
+// path that may not copy from host memory: nothing to stage, nothing to free).
+__global__ void k_setup(const JobDesc d, const GroupDesc g, JobDesc *ddesc, GroupDesc *dgroups) {
+    if (threadIdx.x == 0) {
+        *ddesc = d;
+        *dgroups = g;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 2: the fused tile pass.  Persistent workgroups pull (job, strip) work
 // items of one (norm, m) group from a counter.
@@ -1539,6 +1548,68 @@ Layout layout_of(const Job &jb) {
     return L;
 }
 
+
+// Device descriptor of one job whose work items start at `strip_base` of its
+// group and whose stitch blocks start at `stitch_block0`.
+JobDesc make_desc(const Job &jb, const Layout &lay, int strip_base, int stitch_block0) {
+    const KParams &kp = jb.kp;
+    char *scr = static_cast<char *>(jb.scratch);
+    JobDesc d{};
+    const bool full = jb.mode != kModeAuto;
+    const int64_t hlen = jb.hist_len();
+    const int64_t stride = jb.hist_stride > 0 ? jb.hist_stride : hlen;
+    const int64_t ncols = full ? jb.n_cols : jb.n_vec;
+    d.s = jb.series;
+    d.sb = jb.mode == kModeCross ? jb.series_b : jb.series;
+    d.n_points_b = jb.mode == kModeCross ? jb.n_points_b : jb.n_points;
+    d.bits = jb.bits;
+    d.words = jb.words;
+    d.tail = reinterpret_cast<const float *>(scr + lay.off_tail);
+    d.hd = reinterpret_cast<unsigned long long *>(jb.hist);
+    d.hv = d.hd + stride;
+    d.hw = d.hv + stride;
+    d.flag = jb.flag;
+    d.lead = reinterpret_cast<uint32_t *>(scr + lay.off_lead);
+    d.vfirst = reinterpret_cast<uint16_t *>(scr + lay.off_vf);
+    d.vlast = reinterpret_cast<uint16_t *>(scr + lay.off_vl);
+    d.dfirst = reinterpret_cast<uint16_t *>(scr + lay.off_df);
+    d.dlast = reinterpret_cast<uint16_t *>(scr + lay.off_dl);
+    d.n_points = jb.n_points;
+    d.n = (int32_t)jb.n_vec;
+    d.nb = (int32_t)ncols;
+    d.hmax = (int32_t)(hlen - 1);
+    d.mode = jb.mode;
+    d.m = kp.m;
+    d.tau = kp.tau;
+    d.norm = kp.norm;
+    d.theiler = kp.theiler;
+    d.wp = effective_wp(kp.theiler, jb.n_vec);
+    d.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
+    d.thr0 = kp.d0_bound;
+    d.H = lay.H;
+    d.nstrips = lay.nstrips;
+    d.c_last = (int32_t)((ncols - 1) / 64);
+    d.tail_len = (int32_t)lay.tail_len;
+    d.strip_base = strip_base;
+    d.stitch_block0 = stitch_block0;
+    d.mins[0] = kp.lmin;
+    d.mins[1] = kp.vmin;
+    d.mins[2] = kp.wmin;
+    // 2,048 lengths (8 per thread) per statistics block: the blocks' loops
+    // are chains of dependent loads, so short chains finish sooner.
+    d.stat_blocks = (int32_t)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (hlen + 2047) / 2048));
+    d.stats = jb.stats ? reinterpret_cast<JobStats *>(jb.stats)
+                       : reinterpret_cast<JobStats *>(reinterpret_cast<char *>(jb.flag) + 8);
+    d.ent_part = reinterpret_cast<double *>(scr + lay.off_ent);
+    return d;
+}
+
+int stitch_blocks_of(const Job &jb) {
+    const bool full = jb.mode != kModeAuto;
+    const int64_t lines = full ? jb.n_cols + jb.n_vec + jb.n_cols - 1 : 2 * jb.n_vec;
+    return (int)((lines + kStitchThreads - 1) / kStitchThreads);
+}
+
 }  // namespace
 
 size_t engine_job_scratch_bytes(const Job &job) { return layout_of(job).bytes; }
@@ -1620,7 +1691,6 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     int strip_acc = 0;
     for (int r = 0; r < njobs; ++r) {
         const Job &jb = jobs_in[order[r]];
-        const KParams &kp = jb.kp;
         const Layout lay = layout_of(jb);
         const int key = group_key(jb);
         if (ngroups == 0 || gkeys.back() != key) {
@@ -1632,56 +1702,10 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
             strip_acc = 0;
         }
         hgroups[ngroups - 1].job1 = r + 1;
-        char *scr = static_cast<char *>(jb.scratch);
-        JobDesc d{};
-        const bool full = jb.mode != kModeAuto;
-        const int64_t hlen = jb.hist_len();
-        const int64_t ncols = full ? jb.n_cols : jb.n_vec;
-        d.s = jb.series;
-        d.sb = jb.mode == kModeCross ? jb.series_b : jb.series;
-        d.n_points_b = jb.mode == kModeCross ? jb.n_points_b : jb.n_points;
-        d.bits = jb.bits;
-        d.words = jb.words;
-        d.tail = reinterpret_cast<const float *>(scr + lay.off_tail);
-        d.hd = reinterpret_cast<unsigned long long *>(jb.hist);
-        d.hv = d.hd + hlen;
-        d.hw = d.hv + hlen;
-        d.flag = jb.flag;
-        d.lead = reinterpret_cast<uint32_t *>(scr + lay.off_lead);
-        d.vfirst = reinterpret_cast<uint16_t *>(scr + lay.off_vf);
-        d.vlast = reinterpret_cast<uint16_t *>(scr + lay.off_vl);
-        d.dfirst = reinterpret_cast<uint16_t *>(scr + lay.off_df);
-        d.dlast = reinterpret_cast<uint16_t *>(scr + lay.off_dl);
-        d.n_points = jb.n_points;
-        d.n = (int32_t)jb.n_vec;
-        d.nb = (int32_t)ncols;
-        d.hmax = (int32_t)(hlen - 1);
-        d.mode = jb.mode;
-        d.m = kp.m;
-        d.tau = kp.tau;
-        d.norm = kp.norm;
-        d.theiler = kp.theiler;
-        d.wp = effective_wp(kp.theiler, jb.n_vec);
-        d.thr = kp.norm == RQA_NORM_L2 ? kp.eps_sq : kp.eps;
-        d.thr0 = kp.d0_bound;
-        d.H = lay.H;
-        d.nstrips = lay.nstrips;
-        d.c_last = (int32_t)((ncols - 1) / 64);
-        d.tail_len = (int32_t)lay.tail_len;
-        d.strip_base = strip_acc;
-        d.stitch_block0 = stitch_blocks;
-        d.mins[0] = kp.lmin;
-        d.mins[1] = kp.vmin;
-        d.mins[2] = kp.wmin;
-        // 2,048 lengths (8 per thread) per statistics block: the blocks' loops
-        // are chains of dependent loads, so short chains finish sooner.
-        d.stat_blocks = (int32_t)std::min<int64_t>(kStatMaxBlocks, std::max<int64_t>(1, (hlen + 2047) / 2048));
+        JobDesc d = make_desc(jb, lay, strip_acc, stitch_blocks);
         stat_grid = std::max(stat_grid, (int)d.stat_blocks);
-        d.stats = reinterpret_cast<JobStats *>(reinterpret_cast<char *>(jb.flag) + 8);
-        d.ent_part = reinterpret_cast<double *>(scr + lay.off_ent);
         strip_acc += lay.nstrips;
-        const int64_t lines = full ? ncols + jb.n_vec + ncols - 1 : 2 * jb.n_vec;
-        stitch_blocks += (int)((lines + kStitchThreads - 1) / kStitchThreads);
+        stitch_blocks += stitch_blocks_of(jb);
         hdesc[r] = d;
     }
     hgroups[ngroups - 1].items = strip_acc;
@@ -1741,6 +1765,48 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     hipLaunchKernelGGL(k_stats_entropy, dim3(stat_grid, njobs), dim3(kStatThreads), 0, st, ddesc);
     hipLaunchKernelGGL(k_stats_final, dim3((3 * njobs + 255) / 256), dim3(256), 0, st, ddesc, njobs);
     if (phases) hipEventRecord(phases->ev[3], st);
+    return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
+}
+
+size_t engine_static_bytes(const Job &jb) {
+    return engine_launch_scratch_bytes(1) + a256(kInfoBytes) + layout_of(jb).bytes;
+}
+
+int engine_launch_static(Job jb, void *scratch, hipStream_t st) {
+    if (jb.waves < 1 || jb.waves > kMaxWaves || jb.mode != kModeAuto) return RQA_EINVAL;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return RQA_EDEVICE;
+    // [descriptors | groups | counters][statistics record][job scratch]
+    char *base = static_cast<char *>(scratch);
+    JobDesc *ddesc = reinterpret_cast<JobDesc *>(base);
+    GroupDesc *dgroups = reinterpret_cast<GroupDesc *>(base + a256(sizeof(JobDesc)));
+    int *dcounters = reinterpret_cast<int *>(base + a256(sizeof(JobDesc)) +
+                                             a256(sizeof(GroupDesc) * 64));
+    jb.stats = base + engine_launch_scratch_bytes(1);
+    jb.scratch = base + engine_launch_scratch_bytes(1) + a256(kInfoBytes);
+    const Layout lay = layout_of(jb);
+    const JobDesc d = make_desc(jb, lay, 0, 0);
+    const GroupDesc g{0, 1, lay.nstrips, 0};
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, d, g, ddesc, dgroups);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ddesc, 1, dcounters, 64);
+    hipLaunchKernelGGL(k_prepare, dim3(64, 1), dim3(256), 0, st, ddesc);
+    if (lay.nstrips > 0) {
+        TileKernel kern = tile_kernel(kModeAuto, jb.kp.norm, jb.kp.m);
+        int occ = 0;
+        const size_t lds = strip_lds_bytes(jb.waves);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * jb.waves, lds) != hipSuccess ||
+            occ < 1)
+            occ = 1;
+        const int grid = std::min(ncu * occ, lay.nstrips);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * jb.waves), lds, st, ddesc, dgroups, 0,
+                           dcounters);
+    }
+    hipLaunchKernelGGL(k_stitch, dim3(stitch_blocks_of(jb)), dim3(kStitchThreads), 0, st, ddesc, 1);
+    hipLaunchKernelGGL(k_stats_moments, dim3(d.stat_blocks, 1), dim3(kStatThreads), 0, st, ddesc);
+    hipLaunchKernelGGL(k_stats_entropy, dim3(d.stat_blocks, 1), dim3(kStatThreads), 0, st, ddesc);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, st, ddesc, 1);
     return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
 }
 

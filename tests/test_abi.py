@@ -132,3 +132,21 @@ def test_python_binding_refuses_host_tensors():
     with pytest.raises(TypeError):
         comp.run(np.zeros(100, dtype=np.float32))
     comp.close()
+
+
+def test_run_static_host_errors():
+    """rqa_run_static rejects bad arguments and series beyond its static scratch
+    on the host, before any HIP call (fake device pointers are never touched)."""
+    L = lib()
+    fake = ctypes.c_void_p(0x1000)
+    p = RqaParams(3, 2, 0.1, 2, 2, 2, 2, 1)
+    assert L.rqa_run_static(None, fake, 1000, fake, 1000, fake, None) == -1
+    assert L.rqa_run_static(ctypes.byref(p), None, 1000, fake, 1000, fake, None) == -1
+    assert L.rqa_run_static(ctypes.byref(p), fake, 1000, None, 1000, fake, None) == -1
+    assert L.rqa_run_static(ctypes.byref(p), fake, 1000, fake, 1000, None, None) == -1
+    assert L.rqa_run_static(ctypes.byref(RqaParams(0, 2, 0.1, 2, 2, 2, 2, 1)), fake, 1000, fake,
+                            1000, fake, None) == -1
+    assert L.rqa_run_static(ctypes.byref(p), fake, 4, fake, 10, fake, None) == -2
+    assert L.rqa_run_static(ctypes.byref(p), fake, 1000, fake, 996, fake, None) == -6
+    assert L.rqa_run_static(ctypes.byref(p), fake, 300_000, fake, 300_000, fake, None) == -8
+    assert b"static scratch" in L.rqa_strerror(-8)
