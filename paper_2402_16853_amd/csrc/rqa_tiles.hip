@@ -95,6 +95,15 @@ constexpr int kStitchCapV = 2048; // stitch LDS bins for vertical lengths < kSti
                                   // stitch joins the runs that cross strip edges: long ones)
 constexpr int kStatThreads = 256;
 constexpr int kStatMaxBlocks = 64;
+// Column boxes (exact pruning of the predicate, see tile_bits): per 64-column
+// tile one record of kBoxStride floats holding (lo_k, hi_k) for the first
+// kBoxK coordinates.  The box array of a job starts with a header of
+// kBoxHeader floats whose first word tells whether the job uses the boxes (set
+// by k_box_probe).
+constexpr int kBoxK = 3;
+constexpr int kBoxStride = 8;
+constexpr int kBoxHeader = 64;
+constexpr int kProbeThreads = 256;   // sampled (row block, tile) pairs per job
 
 // Device-side description of one job (one series or window).
 struct JobDesc {
@@ -131,6 +140,7 @@ struct JobDesc {
     int32_t stat_blocks;       // blocks of the statistics kernels for this job
     JobStats *stats;           // device statistics record
     double *ent_part;          // [3][kStatMaxBlocks] entropy partial sums
+    float *box;                // column boxes (header + records), nullptr if none
 };
 
 struct GroupDesc {
@@ -406,6 +416,31 @@ __device__ __forceinline__ uint32_t nonrec_sign_d0(float d0, ConstF col, int tau
     return __float_as_uint(thr - a);
 }
 
+// The same, for column b of a chunk whose coordinate k starts at ck[k].
+template <int NORM, int M>
+__device__ __forceinline__ uint32_t nonrec_sign_rows(const ConstF *ck, int b, const float *xr,
+                                                     float thr) {
+    float a;
+    if (NORM == RQA_NORM_L1) {
+        a = fabsf(ck[0][b] - xr[0]);
+#pragma unroll
+        for (int k = 1; k < M; ++k) a = a + fabsf(ck[k][b] - xr[k]);
+    } else if (NORM == RQA_NORM_L2) {
+        const float d = ck[0][b] - xr[0];
+        a = d * d;
+#pragma unroll
+        for (int k = 1; k < M; ++k) {
+            const float e = ck[k][b] - xr[k];
+            a = a + e * e;
+        }
+    } else {
+        a = fabsf(ck[0][b] - xr[0]);
+#pragma unroll
+        for (int k = 1; k < M; ++k) a = fmaxf(a, fabsf(ck[k][b] - xr[k]));
+    }
+    return __float_as_uint(thr - a);
+}
+
 // Generic embedding dimension: row coordinates read from memory.
 template <int NORM>
 __device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__restrict__ rowp,
@@ -429,19 +464,46 @@ __device__ __forceinline__ uint32_t nonrec_sign_dyn(ConstF col, const float *__r
     return __float_as_uint(thr - a);
 }
 
+// Box test.  `rec` holds, for the first kBoxK coordinates k of a tile's
+// columns, lo_k = the smallest float l with fl(cmin_k - l) <= b and hi_k = the
+// largest float h with fl(h - cmax_k) <= b, where cmin_k / cmax_k are the
+// smallest / largest k-th coordinate of those columns and b is the
+// per-coordinate bound of KParams::d0_bound.  Subtraction is monotone in each
+// operand, so a row coordinate x_k < lo_k (or > hi_k) makes |d_k| > b against
+// every column of the tile, and the accumulated distance, never below its
+// largest term, then exceeds the threshold: the pair is not recurrent.  True
+// when every row of the wave is decided so by some coordinate.
+template <int M>
+__device__ __forceinline__ bool box_decides(ConstF rec, const float *xr) {
+    constexpr int K = M < kBoxK ? M : kBoxK;
+    bool out = false;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out = out | (xr[k] < rec[2 * k]) | (xr[k] > rec[2 * k + 1]);
+    return __builtin_amdgcn_ballot_w64(!out) == 0ull;
+}
+
 // Recurrence bits of one 64x64 tile for this lane's row: bit b <-> column
 // jbase + b.  `cols` points at the coordinate of column jbase (uniform).  The 64
 // columns are taken in eight chunks of 8 (highest first), each fully unrolled,
 // so that at most 8*m column coordinates are live in SGPRs (chunks of 16 left
 // too few SGPRs for the rest of the kernel, which then spilled into VGPR lanes;
-// measured 10% slower).  Each chunk first takes the first coordinate's
-// differences: when no lane of the wave has |d_0| <= thr0 in the chunk, all
-// 8 x 64 pairs are non-recurrent (the bound is exact, see KParams::d0_bound)
-// and the other coordinates are not evaluated.
-template <int NORM, int M>
+// measured 10% slower).
+// Exact pruning, two variants:
+//  * `box` (this tile's box record, or nullptr): when the box decides every
+//    row of the wave, the tile has no recurrent cell and no column is
+//    evaluated.  Otherwise every pair is evaluated: a box test per 8-column
+//    chunk decides far more chunks on smooth series (Lorenz: 64% of the chunks
+//    of undecided tiles, against 24% for the first-coordinate test), but its
+//    record took SGPRs the kernel did not have (spills) and measured slower
+//    than evaluating the chunk;
+//  * D0 (the recurrence plot, and m >= 5): each chunk first takes the first
+//    coordinate's differences; when no lane of the wave has |d_0| <= thr0 in
+//    the chunk, all 8 x 64 pairs are non-recurrent and the other coordinates
+//    are not evaluated.
+template <int NORM, int M, bool D0>
 __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
                                           const float *__restrict__ rowp, int m, float thr_s,
-                                          float thr0_s, uint32_t &lo, uint32_t &hi) {
+                                          float thr0_s, ConstF box, uint32_t &lo, uint32_t &hi) {
     // The thresholds are uniform, but as scalar operands they would make the
     // subtraction and the compare read an SGPR too; VALU instructions with only
     // VGPR operands issue faster on gfx950 (measured: the six-instruction
@@ -449,6 +511,11 @@ __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
     // clock per CU).  The empty asm pins the copies in VGPRs.
     float thr = thr_s, thr0 = thr0_s;
     asm volatile("" : "+v"(thr), "+v"(thr0));
+    if (M > 0 && box != nullptr && box_decides<M>(box, xr)) {
+        lo = 0u;
+        hi = 0u;
+        return;
+    }
 #pragma unroll 1
     for (int half = 1; half >= 0; --half) {
         uint32_t acc = 0;
@@ -457,31 +524,51 @@ __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
             const int b0 = half * 32 + sub * 8;
             ConstF cb = cols + b0;
             if (M > 0) {
-                // All of the chunk's coordinates are loaded up front (the empty
-                // asm keeps the compiler from sinking the loads of the other
-                // coordinates into the branch, which would add a second wait);
-                // the first coordinate's differences decide whether the rest
-                // is evaluated.
-                float d0[8];
+                // Embedding dimensions of 5 and 6 always take the first-
+                // coordinate path: their 40-48 column coordinates do not fit
+                // the SGPRs left, and without the loads pinned ahead of the
+                // test the compiler rebuilt their addresses with long chains
+                // of 64-bit scalar adds (measured 29% slower on the L1, m = 5
+                // windows).
+                if (D0 || M >= 5) {
+                    // All of the chunk's coordinates are loaded up front (the
+                    // empty asm keeps the compiler from sinking the loads of
+                    // the other coordinates into the branch, which would add a
+                    // second wait); the first coordinate's differences decide
+                    // whether the rest is evaluated.
+                    float d0[8];
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    d0[b] = cb[b] - xr[0];
+                    for (int b = 0; b < 8; ++b) {
+                        d0[b] = cb[b] - xr[0];
 #pragma unroll
-                    for (int k = 1; k < (M > 0 ? M : 1); ++k) {
-                        const float ck = cb[b + k * tau];
-                        asm volatile("" ::"s"(ck));
+                        for (int k = 1; k < (M > 0 ? M : 1); ++k) {
+                            const float ck = cb[b + k * tau];
+                            asm volatile("" ::"s"(ck));
+                        }
                     }
-                }
-                const float near =
-                    fminf(fminf(fminf(fabsf(d0[0]), fabsf(d0[1])), fminf(fabsf(d0[2]), fabsf(d0[3]))),
-                          fminf(fminf(fabsf(d0[4]), fabsf(d0[5])), fminf(fabsf(d0[6]), fabsf(d0[7]))));
-                if (__builtin_amdgcn_ballot_w64(near <= thr0) == 0ull) {
-                    acc = (acc << 8) | 0xFFu;
+                    const float near =
+                        fminf(fminf(fminf(fabsf(d0[0]), fabsf(d0[1])), fminf(fabsf(d0[2]), fabsf(d0[3]))),
+                              fminf(fminf(fabsf(d0[4]), fabsf(d0[5])), fminf(fabsf(d0[6]), fabsf(d0[7]))));
+                    if (__builtin_amdgcn_ballot_w64(near <= thr0) == 0ull) {
+                        acc = (acc << 8) | 0xFFu;
+                    } else {
+#pragma unroll
+                        for (int b = 7; b >= 0; --b)
+                            acc = __builtin_amdgcn_alignbit(
+                                acc, nonrec_sign_d0<NORM, M>(d0[b], cb + b, tau, xr, thr), 31);
+                    }
                 } else {
+                    // One uniform pointer per coordinate: each coordinate's 8
+                    // columns are then one s_load_dwordx8 at a fixed offset
+                    // (indexing cb[b + k*tau] instead made the compiler build
+                    // 8*m addresses with 64-bit scalar adds).
+                    ConstF ck[M > 0 ? M : 1];
+#pragma unroll
+                    for (int k = 0; k < (M > 0 ? M : 1); ++k) ck[k] = cb + k * tau;
 #pragma unroll
                     for (int b = 7; b >= 0; --b)
                         acc = __builtin_amdgcn_alignbit(
-                            acc, nonrec_sign_d0<NORM, M>(d0[b], cb + b, tau, xr, thr), 31);
+                            acc, nonrec_sign_rows<NORM, M>(ck, b, xr, thr), 31);
                 }
             } else {
                 for (int b = 7; b >= 0; --b)
@@ -491,6 +578,40 @@ __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
         }
         if (half) hi = ~acc; else lo = ~acc;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Column boxes.  Ordered keys of the non-NaN floats (unsigned order = float
+// order, -0 just below +0), used to bisect over float values.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fkey(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float fval(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+// Largest float h with fl(h - cmax) <= b (h = +inf when b = +inf).
+__device__ float box_hi(float cmax, float b) {
+    if (b == INFINITY) return INFINITY;
+    uint32_t t = fkey(-INFINITY), f = fkey(INFINITY);   // P(t) true, P(f) false
+    while (f - t > 1u) {
+        const uint32_t mid = t + (f - t) / 2u;
+        if (fval(mid) - cmax <= b) t = mid; else f = mid;
+    }
+    return fval(t);
+}
+
+// Smallest float l with fl(cmin - l) <= b (l = -inf when b = +inf).
+__device__ float box_lo(float cmin, float b) {
+    if (b == INFINITY) return -INFINITY;
+    uint32_t f = fkey(-INFINITY), t = fkey(INFINITY);   // Q(f) false, Q(t) true
+    while (t - f > 1u) {
+        const uint32_t mid = f + (t - f) / 2u;
+        if (cmin - fval(mid) <= b) t = mid; else f = mid;
+    }
+    return fval(t);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,6 +642,75 @@ __global__ void k_prepare(const JobDesc *__restrict__ jobs) {
     float *tail = const_cast<float *>(j.tail);
     for (int64_t t = tid; t < j.tail_len; t += stride)
         tail[t] = base + t < j.n_points_b ? j.sb[base + t] : 0.0f;
+}
+
+// Column boxes of every column tile of a job (grid.y = job; one thread per
+// (tile, coordinate)).  Only columns < nb count.
+__global__ void k_box_bounds(const JobDesc *__restrict__ jobs) {
+    const JobDesc &j = jobs[blockIdx.y];
+    if (j.box == nullptr) return;
+    const int K = j.m < kBoxK ? j.m : kBoxK;
+    const int64_t total = (int64_t)(j.c_last + 1) * K;
+    const float b = j.thr0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(t % K);
+        const int64_t c = t / K;
+        const int64_t j0 = c * 64;
+        const int64_t j1 = j0 + 64 < j.nb ? j0 + 64 : j.nb;
+        float cmin = INFINITY, cmax = -INFINITY;
+        const float *col = j.sb + (int64_t)k * j.tau;
+        for (int64_t q = j0; q < j1; ++q) {
+            const float v = col[q];
+            cmin = fminf(cmin, v);
+            cmax = fmaxf(cmax, v);
+        }
+        float *rec = j.box + kBoxHeader + c * kBoxStride;
+        rec[2 * k] = box_lo(cmin, b);
+        rec[2 * k + 1] = box_hi(cmax, b);
+    }
+}
+
+// Whether a job uses its boxes: one block per job samples kProbeThreads
+// (64-row block, column tile) pairs of the evaluated region and counts the
+// tiles whose box decides all 64 rows.  A decided tile saves its whole
+// predicate, an undecided one costs the test (one scalar load and a compare
+// per coordinate), so the boxes are used when at least 1 in 64 sampled tiles
+// is decided.  Only speed depends on this.
+__global__ void __launch_bounds__(kProbeThreads) k_box_probe(const JobDesc *__restrict__ jobs) {
+    const JobDesc &j = jobs[blockIdx.x];
+    if (j.box == nullptr) return;
+    __shared__ int decided, sampled;
+    if (threadIdx.x == 0) { decided = 0; sampled = 0; }
+    __syncthreads();
+    const int K = j.m < kBoxK ? j.m : kBoxK;
+    // splitmix64 of (job, thread): the sample position
+    uint64_t z = ((uint64_t)blockIdx.x << 32) + threadIdx.x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const int blocks = (j.n + 63) / 64;
+    const int r0 = (int)((z & 0xFFFFFFFFull) % (uint64_t)blocks) * 64;
+    const int cmin_tile = j.mode == kModeAuto ? (r0 + j.wp) / 64 : 0;
+    if (cmin_tile <= j.c_last) {
+        const int c = cmin_tile + (int)((z >> 32) % (uint64_t)(j.c_last - cmin_tile + 1));
+        const float *rec = j.box + kBoxHeader + (int64_t)c * kBoxStride;
+        bool all = true;
+        for (int i = r0; i < r0 + 64 && all; ++i) {
+            const int ii = i < j.n ? i : j.n - 1;
+            bool out = false;
+            for (int k = 0; k < K; ++k) {
+                const float x = j.s[ii + (int64_t)k * j.tau];
+                out = out || x < rec[2 * k] || x > rec[2 * k + 1];
+            }
+            all = out;
+        }
+        if (all) atomicAdd(&decided, 1);
+        atomicAdd(&sampled, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        reinterpret_cast<int *>(j.box)[0] = (sampled > 0 && 64 * decided >= sampled) ? 1 : 0;
 }
 
 // Reset the non-finite flags and the work counters (runs before k_prepare).
@@ -632,6 +822,15 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
         return FULL ? (k >= -(R0 + H - 1) && k <= nb - 1 - R0) : (k >= wp && k <= n - 1 - R0);
     };
 
+    // Column boxes of this job, when the probe chose to use them.
+    // (The header is read as a scalar load, so `box` is known to be uniform
+    // and the records are read with scalar loads too.)
+    ConstF box = nullptr;
+    if constexpr (MODE != kModeMatrix && M > 0) {
+        const ConstF bx = to_const(j.box);
+        if (bx != nullptr && __float_as_int(bx[0]) != 0) box = bx + kBoxHeader;
+    }
+
     // Row coordinates of this lane (clamped for rows past the end).
     const int irow = i < n ? i : n - 1;
     const float *rowp = MODE == kModeMatrix ? nullptr : j.s + irow;
@@ -639,6 +838,12 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
     if constexpr (MODE != kModeMatrix) {
 #pragma unroll
         for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? glb(rowp)[(int64_t)k * tau] : 0.0f;
+        // Wait for these loads here, once per strip: gfx950 counts outstanding
+        // global stores and atomics in the same counter as loads, so a wait
+        // for them at their first use inside the tile loop would also wait
+        // for every summary store and histogram atomic still in flight.
+#pragma unroll
+        for (int k = 0; k < (M > 0 ? M : 1); ++k) asm volatile("" : "+v"(xr[k]));
     }
 
     Bins bins{L.bd, L.bv, L.bw};
@@ -675,7 +880,9 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                 xhi = (uint32_t)(word >> 32);
             } else {
                 const ConstF cols = to_const((c == j.c_last) ? j.tail : j.sb + jbase);
-                tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, j.thr0, xlo, xhi);
+                tile_bits<NORM, M, false>(cols, tau, xr, rowp, j.m, j.thr, j.thr0,
+                                          box == nullptr ? nullptr : box + (int64_t)c * kBoxStride,
+                                          xlo, xhi);
             }
 
             // Interior tile: no cell needs masking, and every column and
@@ -1416,7 +1623,7 @@ __global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
         const int jbase = c * 64;
         const ConstF cols = to_const(c == d.col_tiles - 1 ? d.tail : d.b + jbase);
         uint32_t xlo, xhi;
-        tile_bits<NORM, M>(cols, d.tau, xr, rowp, d.m, d.thr, d.thr0, xlo, xhi);
+        tile_bits<NORM, M, true>(cols, d.tau, xr, rowp, d.m, d.thr, d.thr0, nullptr, xlo, xhi);
         uint64_t vm = 0ull;
         if (i < n) {
             const int hv = nb - jbase < 64 ? nb - jbase : 64;
@@ -1495,7 +1702,8 @@ struct Layout {
     int64_t ventries;      // vertical summary entries per array (first, last)
     int64_t dentries;      // diagonal summary entries per array
     int64_t tail_len;
-    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, bytes;
+    int64_t box_floats;    // column boxes (header + records), 0 if none
+    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, off_box, bytes;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1544,6 +1752,12 @@ Layout layout_of(const Job &jb) {
     L.off_df = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
     L.off_dl = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
     L.off_ent = off; off += a256(sizeof(double) * 3 * kStatMaxBlocks);
+    // Boxes for the modes with a predicate and the embedding dimensions whose
+    // row coordinates live in registers.
+    const int64_t ncols = jb.mode == kModeAuto ? n : jb.n_cols;
+    L.box_floats = (jb.mode != kModeMatrix && jb.kp.m <= kMaxM)
+                       ? kBoxHeader + ((ncols - 1) / 64 + 1) * (int64_t)kBoxStride : 0;
+    L.off_box = off; off += a256(sizeof(float) * (size_t)L.box_floats);
     L.bytes = off;
     return L;
 }
@@ -1601,7 +1815,15 @@ JobDesc make_desc(const Job &jb, const Layout &lay, int strip_base, int stitch_b
     d.stats = jb.stats ? reinterpret_cast<JobStats *>(jb.stats)
                        : reinterpret_cast<JobStats *>(reinterpret_cast<char *>(jb.flag) + 8);
     d.ent_part = reinterpret_cast<double *>(scr + lay.off_ent);
+    d.box = lay.box_floats > 0 ? reinterpret_cast<float *>(scr + lay.off_box) : nullptr;
     return d;
+}
+
+// Blocks of k_box_bounds for one job: one thread per box entry, at most 128
+// blocks (the kernel strides over the rest).
+int box_blocks_of(const Layout &lay) {
+    const int64_t entries = lay.box_floats > 0 ? (lay.box_floats - kBoxHeader) / kBoxStride * kBoxK : 0;
+    return (int)std::min<int64_t>(128, std::max<int64_t>(1, (entries + 255) / 256));
 }
 
 int stitch_blocks_of(const Job &jb) {
@@ -1687,6 +1909,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     std::vector<int> gkeys;
     int stitch_blocks = 0;
     int stat_grid = 1;
+    int box_grid = 1;
     int ngroups = 0;
     int strip_acc = 0;
     for (int r = 0; r < njobs; ++r) {
@@ -1704,6 +1927,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         hgroups[ngroups - 1].job1 = r + 1;
         JobDesc d = make_desc(jb, lay, strip_acc, stitch_blocks);
         stat_grid = std::max(stat_grid, (int)d.stat_blocks);
+        box_grid = std::max(box_grid, box_blocks_of(lay));
         strip_acc += lay.nstrips;
         stitch_blocks += stitch_blocks_of(jb);
         hdesc[r] = d;
@@ -1719,6 +1943,8 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     hipLaunchKernelGGL(k_reset, dim3((std::max(njobs, 64) + 255) / 256), dim3(256), 0, st, ddesc,
                        njobs, dcounters, 64);
     hipLaunchKernelGGL(k_prepare, dim3(64, njobs), dim3(256), 0, st, ddesc);
+    hipLaunchKernelGGL(k_box_bounds, dim3(box_grid, njobs), dim3(256), 0, st, ddesc);
+    hipLaunchKernelGGL(k_box_probe, dim3(njobs), dim3(kProbeThreads), 0, st, ddesc);
 
     if (phases) hipEventRecord(phases->ev[1], st);
     int active = 0;
@@ -1792,6 +2018,8 @@ int engine_launch_static(Job jb, void *scratch, hipStream_t st) {
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, d, g, ddesc, dgroups);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ddesc, 1, dcounters, 64);
     hipLaunchKernelGGL(k_prepare, dim3(64, 1), dim3(256), 0, st, ddesc);
+    hipLaunchKernelGGL(k_box_bounds, dim3(box_blocks_of(lay), 1), dim3(256), 0, st, ddesc);
+    hipLaunchKernelGGL(k_box_probe, dim3(1), dim3(kProbeThreads), 0, st, ddesc);
     if (lay.nstrips > 0) {
         TileKernel kern = tile_kernel(kModeAuto, jb.kp.norm, jb.kp.m);
         int occ = 0;
