@@ -7,15 +7,20 @@ Theiler window 1.  value = n_vec^2 recurrence-matrix cells per second (Gcells/s)
 with the series already resident in device memory.
 
 Also reported (outside the timed K steps):
-  roofline      live hipEvent time of the fused tile kernel vs the FP32 vector peak
-                (78.6 T ops/s); traffic = HBM bytes per launch from the committed
-                FETCH_SIZE / WRITE_SIZE summary, null once the kernel changed
+  roofline      live hipEvent time of the fused tile kernel: algorithmic FP32
+                operations (6 per unique pair for L-infinity, m=3) per second
+                vs the FP32 vector peak derived from unit counts and clock
+                (78.6 T ops/s; also vs the published 157.3 TFLOP/s); traffic =
+                HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE
+                summary, null once the kernel changed; executed VALU work from
+                the committed counter summary
   cpu_baseline  the CPU oracle on a bounded sample of the same series
   batched       400 uneven sliding windows of uniform noise in one launch, vs the
                 same windows run one by one
-  served        a Poisson stream (200 req/s) of mixed jobs through the
-                continuous-batching server: p50/p99 latency and Gcells/s, vs the
-                same jobs run one by one
+  served        a Poisson stream (200 req/s, 60 s of arrivals) of mixed jobs
+                through the continuous-batching server: p50/p99 latency and
+                Gcells/s; and its capacity on a closed batch of the jobs vs the
+                same jobs run one by one (no allocation or tuning timed)
   cross / plot / matrix
                 cross recurrence of two Lorenz trajectories (262,144 points each),
                 the packed recurrence plot of 65,536 points, and the RQA of that
@@ -42,26 +47,26 @@ if REPO not in sys.path:
 
 METRIC = "recurrence cells/s (Gcells/s) full RQA @N=1M, 1 GPU; batched p50/p99 latency"
 
-# FP32 vector peak in operations/s.  The published 157.3 TFLOP/s counts a fused
-# multiply-add as two flops: 256 CUs x 2.4 GHz x 128 FP32 lanes per clock per CU
-# x 2.  The predicate's operations (subtract, max, compare) are one operation per
-# lane each, so their peak is 256 x 2.4e9 x 128 = 78.6 T ops/s.
+# FP32 vector peak in operations/s, derived from the unit counts and clock:
+# 256 CUs x 128 FP32 lanes per clock per CU x 2.4 GHz = 78.6 T ops/s.  AMD's
+# published 157.3 TFLOP/s counts each of those lane-operations as a fused
+# multiply-add (2 flops); the predicate's operations (subtract, max, add,
+# compare) are one operation per lane each, so 78.6 T is their ceiling.  The
+# bench line also gives the fraction against the published figure.
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
-# Sustained rate of the predicate's own instruction stream (L-infinity, m=3:
-# 6 VALU per column, threshold in a VGPR, 1.42 wave-instructions per clock per
-# CU at eight waves per SIMD), measured with --probe-valu on the MI355X: the
-# practical ceiling of the tile kernel.
-PREDICATE_CEILING_TOPS = 55.4
+PUBLISHED_FP32_TFLOPS = 157.3
 TILES_SRC = os.path.join(REPO, "paper_2402_16853_amd", "csrc", "rqa_tiles.hip")
+CALIB_SRC = os.path.join(REPO, "paper_2402_16853_amd", "csrc", "calib.hip")
 PMC_SUMMARY = os.path.join(REPO, "profiles", "k_tiles_lorenz_N1048576_pmc.md")
+VALU_PROBE_SUMMARY = os.path.join(REPO, "profiles", "valu_issue_probe.md")
 
 
-def profile_fields():
-    """Figures of the committed k_tiles counter summary, or {} when the kernel
-    source has changed since the counters were taken."""
+def summary_fields(path, src):
+    """The "- key: value" lines of a committed profile summary, or {} when the
+    source it was measured with (sha256 recorded in the summary) has changed."""
     import hashlib
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return {}
     fields = {}
@@ -69,8 +74,26 @@ def profile_fields():
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    sha = hashlib.sha256(open(TILES_SRC, "rb").read()).hexdigest()
-    return fields if fields.get("kernel source sha256") == sha else {}
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return fields if fields.get("source sha256") == sha else {}
+
+
+def predicate_ceiling():
+    """Sustained issue rate of the predicate's own instruction stream
+    (libcalib.so, committed probe summary), or None if stale."""
+    f = summary_fields(VALU_PROBE_SUMMARY, CALIB_SRC)
+    try:
+        return {"tops": float(f["predicate ceiling T ops/s"]),
+                "valu_per_clk_per_cu": float(f["VALU wave-instructions per clock per CU"]),
+                "source": "profiles/valu_issue_probe.md (bench.py --probe-valu)"}
+    except (KeyError, ValueError):
+        return None
+
+
+def profile_fields():
+    """Figures of the committed k_tiles counter summary, or {} when the kernel
+    source has changed since the counters were taken."""
+    return summary_fields(PMC_SUMMARY, TILES_SRC)
 
 
 def measured_traffic():
@@ -82,20 +105,22 @@ def measured_traffic():
         return None
 
 
-def measured_pruning(achieved_tops, ops_per_pair):
-    """Share of 8-column chunks whose predicate the tile kernel evaluated in full
-    (the rest are decided by the first coordinate alone), from the committed
-    counter summary, and the rate of the operations actually executed."""
+def measured_valu(kernel_ms):
+    """VALU work the tile kernel executed (committed counter summary): wave-
+    instructions per launch and the lane-operation rate of this run's kernel
+    time against the 78.6 T peak.  The predicate is pruned exactly (whole
+    tiles are skipped when a column box rules out every row), so the executed
+    rate differs from the algorithmic one."""
+    f = profile_fields()
     try:
-        full = float(profile_fields()["full-evaluation chunk fraction"])
+        insts = float(f["VALU wave-instructions per launch"])
+        util = float(f["VALU lane utilisation"])
     except (KeyError, ValueError):
         return None
-    # per pair: all ops_per_pair in a full chunk; in a pruned chunk one
-    # subtraction and one comparison (the wave-wide minimum test)
-    executed = full * ops_per_pair + (1.0 - full) * 2.0
-    return {"full_chunk_frac": full, "executed_ops_per_pair": round(executed, 3),
-            "executed_tops": round(achieved_tops * executed / ops_per_pair, 3),
-            "executed_frac": round(achieved_tops * executed / ops_per_pair / VALU_PEAK_TOPS, 4)}
+    tops = insts * 64 * util / (kernel_ms * 1e-3) / 1e12
+    return {"valu_insts_per_launch": insts, "lane_utilisation": util,
+            "executed_lane_ops_tops": round(tops, 3),
+            "executed_frac": round(tops / VALU_PEAK_TOPS, 4)}
 
 
 def measured_lds(kernel_ms):
@@ -198,15 +223,17 @@ def bench_headline(args, torch, RQA, workload):
     achieved = ops / (tile_ms * 1e-3) / 1e12
     log(f"[bench] {ms:.2f} ms/step  tiles {tile_ms:.2f} ms  stitch {np.mean(stitch):.2f} ms  "
         f"prepare {np.mean(prep):.2f} ms  RR={res.measures['rr']:.6f} DET={res.measures['det']:.6f}")
+    ceiling = predicate_ceiling()
+    if ceiling:
+        ceiling["frac"] = round(achieved / ceiling["tops"], 4)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "TFLOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
             "traffic": measured_traffic(),
+            "frac_vs_published_fp32": round(achieved / PUBLISHED_FP32_TFLOPS, 4),
+            "published_fp32_tflops": PUBLISHED_FP32_TFLOPS,
             "lds": measured_lds(tile_ms),
-            "pruning": measured_pruning(achieved, ops_per_pair(p.m, p.norm)),
-            "frac_vs_64_lanes": round(achieved / (VALU_PEAK_TOPS / 2), 4),
-            "predicate_ceiling": {"tops": PREDICATE_CEILING_TOPS,
-                                  "frac": round(achieved / PREDICATE_CEILING_TOPS, 4),
-                                  "source": "bench.py --probe-valu (libcalib.so)"},
+            "executed": measured_valu(tile_ms),
+            "predicate_ceiling": ceiling,
             "kernel": "k_tiles<Linf,m=3>", "kernel_ms": round(tile_ms, 3),
             "ops_per_launch": ops,
             "stitch_ms": round(float(np.mean(stitch)), 3),
@@ -283,7 +310,10 @@ def bench_batched(args, torch, RQA, workload, windows_plan):
     # the same windows, one launch each
     single = RQA.from_params(p)
     views = [ds[int(o):int(o) + int(L)] for o, L in zip(off, ln)]
-    for v in views[:8]:
+    # every window once before timing, so that the autotuner has settled for
+    # every size class (each class sees its candidate shapes) and the
+    # handle's workspace has reached its largest size
+    for v in views:
         single.run(v)
         single.result(histograms=False)
     torch.cuda.synchronize()
@@ -412,16 +442,33 @@ def bench_paper_e2(args, torch, RQA, workload):
     return out
 
 
-def bench_served(args, torch, RQA, Server, served_requests):
-    reqs = served_requests(args.requests, rate_hz=200.0, seed=args.seed)
+def default_waves(n_vec: int) -> int:
+    """Waves per workgroup the server uses for a job of n_vec delay vectors
+    (the library's default shape: 8 from 32,768 vectors, else 4)."""
+    return 8 if n_vec >= 4096 * 8 else 4
+
+
+def bench_served(args, torch, RQA, Server, reqs):
+    """Latency of a Poisson stream through the continuous-batching server, and
+    its capacity against the same jobs run one at a time.
+
+    * Poisson: every request submitted at its arrival time (200 req/s, at least
+      60 s of arrivals by default), latency = submit to result on the host.
+    * capacity: the first `capacity_requests` jobs submitted at once (closed
+      loop), total time to the last result.
+    * sequential: the same jobs one after another through rqa_run +
+      rqa_result, each on a handle created, shaped like the server's (fixed
+      workgroup shape, no autotuning trials) and run once before the timed run
+      (so no allocation is timed, as the server's pool allocates nothing per
+      job); the sum of the timed runs."""
     dev = torch.device("cuda:0")
     dser = [torch.from_numpy(r.series).to(dev) for r in reqs]
     torch.cuda.synchronize()
-    cells = float(sum((len(r.series) - (r.params.m - 1) * r.params.tau) ** 2 for r in reqs))
+    nvec = [len(r.series) - (r.params.m - 1) * r.params.tau for r in reqs]
+    cells = float(sum(float(v) * v for v in nvec))
     budget = 16 << 30
     srv = Server(budget, streams=4)
     log(f"[bench] served: {len(reqs)} requests over {reqs[-1].arrival:.2f} s, {cells:.3e} cells")
-    # warm-up: a few jobs
     for r, d in list(zip(reqs, dser))[:4]:
         srv.wait(srv.submit(r.params, d), histograms=False)
     lat = []
@@ -444,46 +491,76 @@ def bench_served(args, torch, RQA, Server, served_requests):
         if not done:
             time.sleep(0.0002)
     span = time.perf_counter() - t_start
-    srv.close()
-    # the same jobs, one at a time
+    # capacity: a closed batch of the first jobs
+    nc = min(args.capacity_requests, len(reqs))
+    cap_cells = float(sum(float(v) * v for v in nvec[:nc]))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for r, d in zip(reqs, dser):
+    tickets = [srv.submit(r.params, d) for r, d in zip(reqs[:nc], dser[:nc])]
+    for t in tickets:
+        srv.wait(t, histograms=False)
+    t_cap = time.perf_counter() - t0
+    srv.close()
+    # the same jobs one at a time, untimed allocation and shape
+    t_seq = 0.0
+    for r, d, n in zip(reqs[:nc], dser[:nc], nvec[:nc]):
         c = RQA.from_params(r.params)
+        c.set_tiling(default_waves(n), 0)
         c.run(d)
         c.result(histograms=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.run(d)
+        c.result(histograms=False)
+        t_seq += time.perf_counter() - t0
         c.close()
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
     lat_ms = np.array(lat) * 1e3
-    return {"requests": len(reqs), "rate_hz": 200.0, "cells": cells,
+    return {"requests": len(reqs), "rate_hz": 200.0, "arrival_span_s": round(reqs[-1].arrival, 3),
+            "cells": cells, "latency_samples": int(len(lat_ms)),
             "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3),
+            "p99_rank_from_top": int(round(0.01 * len(lat_ms))),
             "span_s": round(span, 3), "gcells_per_s": round(cells / span / 1e9, 3),
-            "sequential_busy_s": round(ts, 3),
-            "sequential_gcells_per_s": round(cells / ts / 1e9, 3)}
+            "capacity": {"requests": nc, "cells": cap_cells, "s": round(t_cap, 3),
+                         "gcells_per_s": round(cap_cells / t_cap / 1e9, 3),
+                         "sequential_s": round(t_seq, 3),
+                         "sequential_gcells_per_s": round(cap_cells / t_seq / 1e9, 3),
+                         "speedup_vs_sequential": round(t_seq / t_cap, 3)}}
 
 
 def probe_valu():
     """Sustained issue rate of the predicate loop alone (16 columns per trip:
     96 predicate VALU instructions + 1 bookkeeping), as wave-instructions per
-    clock per CU at 2.4 GHz and as FP32 algorithmic ops/s (6 per column-lane)."""
+    clock per CU at 2.4 GHz and as FP32 algorithmic ops/s (6 per column-lane),
+    over grids from one workgroup per CU up to 32 per CU (the median of three
+    launches each); the last line gives the largest rate, the ceiling."""
     import ctypes
     lib = ctypes.CDLL(os.path.join(REPO, "paper_2402_16853_amd", "libcalib.so"))
     lib.calib_predicate.restype = ctypes.c_int
     lib.calib_predicate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_double)]
     iters = 4000
-    for blocks, threads in ((256, 512), (512, 512), (768, 512), (1024, 512), (1024, 256),
-                            (2048, 256)):
-        ms = ctypes.c_double()
-        rc = lib.calib_predicate(blocks, threads, iters, ctypes.byref(ms))
+    best = None
+    for blocks, threads in ((256, 512), (512, 512), (768, 512), (1024, 512), (1536, 512),
+                            (2048, 512), (3072, 512), (4096, 512), (8192, 512),
+                            (1024, 256), (2048, 256), (4096, 256), (8192, 256)):
+        runs = []
+        for _ in range(3):
+            ms = ctypes.c_double()
+            rc = lib.calib_predicate(blocks, threads, iters, ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"calib_predicate failed ({rc})")
+            runs.append(ms.value)
+        t = float(np.median(runs))
         waves = blocks * threads // 64
-        instr = waves * iters * 97.0
-        rate = instr / (ms.value * 1e-3) / 256 / 2.4e9
-        ops = waves * iters * 16 * 6 * 64 / (ms.value * 1e-3) / 1e12
-        print(json.dumps({"probe": "valu", "blocks": blocks, "threads": threads, "rc": rc,
-                          "ms": round(ms.value, 3), "valu_per_clk_per_cu_at_2.4GHz": round(rate, 3),
-                          "predicate_tops": round(ops, 3)}), flush=True)
+        rate = waves * iters * 97.0 / (t * 1e-3) / 256 / 2.4e9
+        ops = waves * iters * 16 * 6 * 64 / (t * 1e-3) / 1e12
+        rec = {"probe": "valu", "blocks": blocks, "threads": threads, "ms": round(t, 3),
+               "valu_per_clk_per_cu_at_2.4GHz": round(rate, 3), "predicate_tops": round(ops, 3)}
+        print(json.dumps(rec), flush=True)
+        if best is None or ops > best["predicate_tops"]:
+            best = rec
+    print(json.dumps({"probe": "valu", "ceiling": best}), flush=True)
 
 
 def probe_lds():
@@ -513,7 +590,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-points", type=int, default=300_000)
-    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--requests", type=int, default=12_000,
+                    help="served requests (200 req/s: 12,000 = 60 s of arrivals)")
+    ap.add_argument("--capacity-requests", type=int, default=2_000,
+                    help="served jobs of the closed-loop capacity run and its sequential baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
@@ -536,6 +616,21 @@ def main():
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(phase, flag):
+        return not args.quick and not flag and (not only or phase in only)
+
+    reqs = None
+    if not (args.probe_valu or args.probe_lds or args.probe_copy) and want("served", args.no_served):
+        # Made before anything touches the GPU: the series come from forked
+        # worker processes.
+        from workloads import served_requests
+        t0 = time.perf_counter()
+        reqs = served_requests(args.requests, rate_hz=200.0, seed=args.seed,
+                               workers=min(16, os.cpu_count() or 1))
+        log(f"[bench] served stream: {len(reqs)} requests made in {time.perf_counter() - t0:.1f} s")
+
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -556,19 +651,14 @@ def main():
         log(f"[probe] copied {args.probe_copy} MiB three times")
         return
     from paper_2402_16853_amd import RQA, Server
-    from workloads import workload, windows_plan, served_requests
-
-    only = set(x for x in args.only.split(",") if x)
-
-    def want(phase, flag):
-        return not args.quick and not flag and (not only or phase in only)
+    from workloads import workload, windows_plan
 
     hl = bench_headline(args, torch, RQA, workload)
     extra = {}
     if want("batched", args.no_batched):
         extra["batched"] = bench_batched(args, torch, RQA, workload, windows_plan)
     if want("served", args.no_served):
-        extra["served"] = bench_served(args, torch, RQA, Server, served_requests)
+        extra["served"] = bench_served(args, torch, RQA, Server, reqs)
     if want("full", False):
         extra.update(bench_full_matrices(args, torch, RQA, workload))
     if want("e2", False):

@@ -20,6 +20,9 @@ ERRORS = {
 }
 EAGAIN = -9
 ENONFINITE = -5
+RQA_EINVAL = -1
+RQA_ESIZE = -6
+RQA_ESTATE = -7
 
 
 class RqaParams(ctypes.Structure):

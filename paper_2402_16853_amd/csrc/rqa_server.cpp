@@ -39,52 +39,13 @@
 #include <vector>
 
 #include "rqa_internal.h"
+#include "rqa_policy.h"
 
 using namespace rqa;
 
 namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// First-fit allocator over [0, size) with a coalescing free list.
-class Pool {
-public:
-    void reset(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t *off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t start = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[start] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-private:
-    std::map<size_t, size_t> free_;
-};
 
 enum JobState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
 
@@ -105,7 +66,6 @@ struct ServedJob {
 };
 
 constexpr size_t kMaxBatch = 256;
-constexpr double kBigCells = 2.0e9;   // jobs above this (~45k vectors) launch alone
 
 double job_cells(const ServedJob *j) { return static_cast<double>(j->n_vec) * j->n_vec; }
 constexpr size_t kInfoWords = kInfoBytes / sizeof(uint64_t);
@@ -194,30 +154,24 @@ void on_launch_done(void *arg) {
 // small ones.  Entered and left with `lk` held; the HIP calls run with it
 // released.  Returns the number of jobs launched.
 size_t admit_and_launch(rqa_server *srv, std::unique_lock<std::mutex> &lk) {
+    std::deque<AdmitJob> queue;
+    for (const ServedJob *j : srv->pending) {
+        queue.push_back(AdmitJob{job_cells(j), j->footprint});
+        if (queue.size() >= kMaxBatch) break;
+    }
+    const Admission adm = plan_launch(queue, srv->pool, kMaxBatch);
+    if (adm.offsets.empty()) return 0;
     std::vector<ServedJob *> batch;
-    double cells = 0.0;
-    while (!srv->pending.empty() && batch.size() < kMaxBatch) {
+    for (size_t off : adm.offsets) {
         ServedJob *j = srv->pending.front();
-        const bool big = job_cells(j) > kBigCells;
-        if (big && !batch.empty()) break;   // it starts the next launch
-        size_t off = 0;
-        if (!srv->pool.alloc(j->footprint, &off)) break;
+        srv->pending.pop_front();
         j->off = off;
         j->state = kRunning;
-        srv->pending.pop_front();
         batch.push_back(j);
-        cells += job_cells(j);
-        if (big) break;
     }
-    if (batch.empty()) return 0;
-    // The stream of the launch's class with the least work in flight.
-    const bool big = batch.size() == 1 && cells > kBigCells;
-    const size_t ns = srv->streams.size();
-    const size_t half = ns > 1 ? ns / 2 : 1;
-    const size_t lo = (big || ns == 1) ? 0 : half, hi = big ? half : ns;
-    size_t slot = lo;
-    for (size_t c = lo + 1; c < hi; ++c)
-        if (srv->load[c] < srv->load[slot]) slot = c;
+    const double cells = adm.cells;
+    const bool big = adm.big;
+    const size_t slot = pick_stream(srv->load, big);
     srv->load[slot] += cells;
     ++srv->inflight;
     lk.unlock();

@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <vector>
@@ -141,6 +142,9 @@ struct JobDesc {
     JobStats *stats;           // device statistics record
     double *ent_part;          // [3][kStatMaxBlocks] entropy partial sums
     float *box;                // column boxes (header + records), nullptr if none
+    int32_t spin_limit;        // polls before a neighbour wait gives up (kSpinLimit)
+    int32_t wait_bias;         // added to every wait target: 0, or (fault injection
+                               // for tests) a bias no counter reaches
 };
 
 struct GroupDesc {
@@ -757,13 +761,13 @@ __host__ __device__ constexpr size_t strip_lds_bytes(int waves) {
 }
 
 // Wait (wave-uniform) until the counter reaches `target`.  Each wait is bounded:
-// past kSpinLimit polls it gives up and returns false, so a wave never hangs.
-__device__ __forceinline__ bool wait_counter(int *ctr, int target) {
+// past `limit` polls it gives up and returns false, so a wave never hangs.
+__device__ __forceinline__ bool wait_counter(int *ctr, int target, uint32_t limit) {
     for (uint32_t spin = 0;; ++spin) {
         const int v = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
         if (v >= target) return true;
-        if (spin >= kSpinLimit) return false;
+        if (spin >= limit) return false;
         __builtin_amdgcn_s_sleep(1);
     }
 }
@@ -931,8 +935,11 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
             // This tile's carries from the wave above, and a free slot below.
             // After one wait has given up the wave stops waiting (the job is
             // flagged as failed), so a strip finishes in bounded time.
-            if (wave > 0 && sync_ok) sync_ok = wait_counter(&L.prod[wave - 1], t + 1);
-            if (wave < nw - 1 && sync_ok) sync_ok = wait_counter(&L.cons[wave], t - kRing + 1);
+            if (wave > 0 && sync_ok)
+                sync_ok = wait_counter(&L.prod[wave - 1], t + 1 + j.wait_bias, (uint32_t)j.spin_limit);
+            if (wave < nw - 1 && sync_ok)
+                sync_ok = wait_counter(&L.cons[wave], t - kRing + 1 + j.wait_bias,
+                                       (uint32_t)j.spin_limit);
 
             if (interior && !any) {
                 // No recurrence in an interior tile: every open run sees 64
@@ -1816,6 +1823,14 @@ JobDesc make_desc(const Job &jb, const Layout &lay, int strip_base, int stitch_b
                        : reinterpret_cast<JobStats *>(reinterpret_cast<char *>(jb.flag) + 8);
     d.ent_part = reinterpret_cast<double *>(scr + lay.off_ent);
     d.box = lay.box_floats > 0 ? reinterpret_cast<float *>(scr + lay.off_box) : nullptr;
+    // Fault injection for tests of the give-up path: with
+    // RQA_DEBUG_WAIT_GIVEUP=1 in the environment every neighbour wait of the
+    // tile kernel aims at a count no wave reaches and gives up after 64
+    // polls; the kernels still finish and the job reports RQA_EDEVICE.
+    const char *giveup = std::getenv("RQA_DEBUG_WAIT_GIVEUP");
+    const bool inject = giveup && giveup[0] == '1';
+    d.spin_limit = inject ? 64 : (int32_t)kSpinLimit;
+    d.wait_bias = inject ? (1 << 30) : 0;
     return d;
 }
 

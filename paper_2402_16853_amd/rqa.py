@@ -13,7 +13,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from ._lib import RQA_OK, ENONFINITE, RqaMeasures, RqaParams, check, lib, EAGAIN, RQAError
+from ._lib import (RQA_OK, RQA_EINVAL, RQA_ESIZE, RQA_ESTATE, ENONFINITE, RqaMeasures,
+                   RqaParams, check, lib, EAGAIN, RQAError)
 
 NORMS = {"l1": 1, "taxicab": 1, "manhattan": 1, "l2": 2, "euclidean": 2,
          "linf": 3, "maximum": 3, "chebyshev": 3, 1: 1, 2: 2, 3: 3}
@@ -284,7 +285,9 @@ class RQA:
         status = np.zeros(count, dtype=np.int32)
         rc = lib().rqa_result_batch_all(self._h, ctypes.cast(out, ctypes.c_void_p),
                                         status.ctypes.data_as(ctypes.c_void_p), count)
-        if rc not in (RQA_OK, ENONFINITE):
+        # A window's own failure is in its status; only errors of the call
+        # itself raise (no run, count mismatch, bad arguments).
+        if rc in (RQA_EINVAL, RQA_ESTATE, RQA_ESIZE):
             check(rc, "rqa_result_batch_all")
         return np.ctypeslib.as_array(out).copy(), status
 

@@ -134,7 +134,7 @@ def main_served_large(count=400, seed=0, largest=16):
     eps at RR ~ 5%), keyed by request index: the jobs that set the served
     latency tail."""
     from workloads import served_requests
-    reqs = served_requests(count, rate_hz=200.0, seed=seed)
+    reqs = served_requests(count, rate_hz=200.0, seed=seed, workers=8)
     pick = sorted(sorted(range(count), key=lambda k: -len(reqs[k].series))[:largest])
     t0 = time.time()
     jobs = []

@@ -42,14 +42,17 @@ def test_windows400_sample():
 
 
 def test_served_large_sample():
+    """The stored jobs are the 16 longest of the first 400 requests, with the
+    parameters and series the generator makes; the shortest is recomputed."""
     g = _load("served_large_seed0_digest.json")
-    reqs = served_requests(g["count"], rate_hz=g["rate_hz"], seed=g["seed"])
+    reqs = served_requests(g["count"], rate_hz=g["rate_hz"], seed=g["seed"], workers=4)
+    longest = sorted(sorted(range(g["count"]), key=lambda k: -len(reqs[k].series))[:16])
+    assert [rec["request"] for rec in g["jobs"]] == longest
     import hashlib
     for rec in g["jobs"]:
         r = reqs[rec["request"]]
         assert r.params.asdict() == rec["params"]
         assert hashlib.sha256(r.series.tobytes()).hexdigest()[:16] == rec["series_sha_prefix"]
-    # the smallest stored job, recomputed
     rec = min(g["jobs"], key=lambda x: x["n_points"])
     r = reqs[rec["request"]]
     _same(*oracle.rqa(r.series, r.params), rec)

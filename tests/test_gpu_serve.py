@@ -121,35 +121,39 @@ def test_poll_before_done_and_nonfinite(cuda):
 def test_served_stream_largest_jobs_match_oracle(cuda, oracle_lib):
     """The 16 longest jobs among the first 400 requests of the served benchmark
     stream (up to 2e5 points each, mixed m, tau, norm; eps at RR ~ 5%), served
-    in a mix with the stream's short jobs: each equals the oracle (digests of
-    its dense histograms stored by tests/golden/make_golden.py, which calls only
-    the oracle), and the short ones equal the oracle computed here."""
+    in a mix with short jobs: each equals the oracle (digests of its dense
+    histograms stored by tests/golden/make_golden.py, which calls only the
+    oracle), and the short ones equal the oracle computed here."""
     import json
     import os
 
     import torch
     from golden_digest import check_record
     from paper_2402_16853_amd import Server
+    from workloads import served_request
     g = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                                     "served_large_seed0_digest.json")))
-    reqs = served_requests(g["count"], rate_hz=g["rate_hz"], seed=g["seed"])
-    big = {rec["request"]: rec for rec in g["jobs"]}
-    small = [k for k in range(g["count"]) if len(reqs[k].series) <= 3000][:48]
-    order = sorted(list(big) + small)
-    dser = {k: torch.from_numpy(reqs[k].series).to(cuda) for k in order}
+    big = [served_request(rec["request"], 0.0, g["seed"]) for rec in g["jobs"]]
+    small = served_requests(48, rate_hz=2000.0, seed=17, min_len=300, max_len=3000)
+    mix = []
+    for k in range(max(len(big), len(small))):
+        if k < len(small):
+            mix.append(("small", k, small[k]))
+        if k < len(big):
+            mix.append(("big", k, big[k]))
+    dser = [torch.from_numpy(r.series).to(cuda) for _, _, r in mix]
     torch.cuda.synchronize()
     srv = Server(16 << 30, streams=4)
     _announce("serve-stream-largest", large=len(big), small=len(small))
-    tickets = {k: srv.submit(reqs[k].params, dser[k]) for k in order}
-    served = {k: srv.wait(t) for k, t in tickets.items()}
+    tickets = [srv.submit(r.params, d) for (_, _, r), d in zip(mix, dser)]
+    served = [srv.wait(t) for t in tickets]
     srv.close()
-    for k in order:
-        r = reqs[k]
-        if k in big:
-            assert r.params.asdict() == big[k]["params"]
-            check_record(served[k], big[k], f"request {k} n={len(r.series)}")
+    for (kind, k, r), got in zip(mix, served):
+        if kind == "big":
+            rec = g["jobs"][k]
+            assert r.params.asdict() == rec["params"]
+            check_record(got, rec, f"request {rec['request']} n={len(r.series)}")
         else:
             ref = oracle_lib.histograms(r.series, r.params.m, r.params.tau, r.params.eps,
                                         r.params.norm, r.params.theiler)
-            got = served[k]
             assert all(np.array_equal(x, y) for x, y in zip((got.diag, got.vert, got.white), ref)), k

@@ -22,5 +22,6 @@ up to about a million points, fixed radius, minimum line lengths of 2):
 from .series import (  # noqa: F401
     NORM_L1, NORM_L2, NORM_LINF, Params,
     logistic_series, ar1_seasonal_series, lorenz_x_series, uniform_series,
-    sine_series, corner_lines, workload, windows_plan, served_requests, n_vectors,
+    sine_series, corner_lines, workload, windows_plan, served_requests, served_request,
+    n_vectors,
 )

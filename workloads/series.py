@@ -207,34 +207,53 @@ class Request:
     kind: str
 
 
-def served_requests(count: int, rate_hz: float = 200.0, seed: int = 0,
-                    min_len: int = 1_000, max_len: int = 200_000, target_rr: float = 0.05):
-    """Poisson stream of independent seeded series: half logistic maps with
-    r ~ U(3.6, 4.0), half AR(1) with phi ~ U(0.5, 0.99); lengths log-uniform in
+def served_request(rid: int, arrival: float = 0.0, seed: int = 0, min_len: int = 1_000,
+                   max_len: int = 200_000, target_rr: float = 0.05) -> Request:
+    """Request ``rid`` of the served stream: an independent series drawn from
+    its own generator (seeded by (seed, rid)), so that any request can be made
+    alone and a stream can be made in parallel.  Half logistic maps with
+    r ~ U(3.6, 4.0), half AR(1) with phi ~ U(0.5, 0.99); length log-uniform in
     [min_len, max_len]; m ~ U{2,3,4}, tau ~ U{1..8}, norm ~ U{L1, L2, Linf};
-    eps = fl32 of the ``target_rr`` quantile of distances over 2^16 random pairs."""
-    rng = np.random.default_rng(seed + 104729)
-    t = 0.0
-    out = []
-    for rid in range(count):
-        t += rng.exponential(1.0 / rate_hz)
-        m = int(rng.integers(2, 5))
-        tau = int(rng.integers(1, 9))
-        norm = int(rng.integers(1, 4))
-        length = int(round(math.exp(rng.uniform(math.log(min_len), math.log(max_len)))))
-        length = max(length, (m - 1) * tau + 2)
-        if rid % 2 == 0:
-            r = rng.uniform(3.6, 4.0)
-            s = logistic_series(length, r, rng.uniform(0.05, 0.95))
-            kind = "logistic"
-        else:
-            phi = rng.uniform(0.5, 0.99)
-            y = ar1_series(length, phi, rng)
-            sd = y.std()
-            y = (y - y.mean()) / (sd if sd > 0 else 1.0)
-            s = _f32(y)
-            kind = "ar1"
-        d = _pair_distances_fp64(s, m, tau, norm, 1 << 16, rng)
-        eps = float(np.float32(np.quantile(d, target_rr)))
-        out.append(Request(rid, t, s, Params(m=m, tau=tau, eps=eps, norm=norm), kind))
-    return out
+    eps = fl32 of the ``target_rr`` quantile of distances over 2^16 random
+    pairs."""
+    rng = np.random.default_rng([seed + 104729, rid])
+    m = int(rng.integers(2, 5))
+    tau = int(rng.integers(1, 9))
+    norm = int(rng.integers(1, 4))
+    length = int(round(math.exp(rng.uniform(math.log(min_len), math.log(max_len)))))
+    length = max(length, (m - 1) * tau + 2)
+    if rid % 2 == 0:
+        r = rng.uniform(3.6, 4.0)
+        s = logistic_series(length, r, rng.uniform(0.05, 0.95))
+        kind = "logistic"
+    else:
+        phi = rng.uniform(0.5, 0.99)
+        y = ar1_series(length, phi, rng)
+        sd = y.std()
+        y = (y - y.mean()) / (sd if sd > 0 else 1.0)
+        s = _f32(y)
+        kind = "ar1"
+    d = _pair_distances_fp64(s, m, tau, norm, 1 << 16, rng)
+    eps = float(np.float32(np.quantile(d, target_rr)))
+    return Request(rid, arrival, s, Params(m=m, tau=tau, eps=eps, norm=norm), kind)
+
+
+def _served_one(args):
+    return served_request(*args)
+
+
+def served_requests(count: int, rate_hz: float = 200.0, seed: int = 0,
+                    min_len: int = 1_000, max_len: int = 200_000, target_rr: float = 0.05,
+                    workers: int = 1):
+    """Poisson stream of ``count`` independent seeded requests (see
+    ``served_request``) at ``rate_hz``: the inter-arrival times come from a
+    generator of their own.  ``workers`` > 1 makes the series in that many
+    forked processes (the result is the same)."""
+    gaps = np.random.default_rng([seed + 104729, 1 << 40]).exponential(1.0 / rate_hz, size=count)
+    arrivals = np.cumsum(gaps)
+    jobs = [(rid, float(arrivals[rid]), seed, min_len, max_len, target_rr) for rid in range(count)]
+    if workers > 1 and count > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            return pool.map(_served_one, jobs, chunksize=max(1, count // (8 * workers)))
+    return [_served_one(j) for j in jobs]
