@@ -424,6 +424,7 @@ def bench_paper_e2(args, torch, RQA, workload):
     for w in (1, 0):
         q = type(p)(m=p.m, tau=p.tau, eps=p.eps, norm=p.norm, lmin=2, vmin=2, wmin=2, theiler=w)
         comp = RQA.from_params(q)
+        settle(comp, lambda: comp.run(ds), lambda: comp.result(histograms=False))
         comp.run(ds)
         comp.result(histograms=True)
         t = []
