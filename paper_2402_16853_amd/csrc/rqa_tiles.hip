@@ -133,6 +133,9 @@ struct JobDesc {
     float thr0;                // first-coordinate bound (KParams::d0_bound)
     int32_t H;                 // strip height
     int32_t nstrips;
+    int32_t segs;              // full matrix: column segments per strip (auto: 1)
+    int32_t seg_tiles;         // column tiles per segment (>= H/64 and >= 8)
+    int32_t dw;                // full matrix: diagonal summary slots per (strip, segment) block
     int32_t c_last;            // last column tile (nb-1)/64
     int32_t tail_len;          // floats in tail
     int32_t strip_base;        // first work item of this job within its group
@@ -798,7 +801,7 @@ __device__ void flush_bins(const StripLds &L, const JobDesc &j) {
 // kModeMatrix: a full n x nb matrix that is not symmetric (every diagonal and
 // every column walked once; no horizontal runs).
 template <int NORM, int M, int MODE>
-__device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
+__device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     static_assert(kMaxWaves <= 8, "LDS budget assumes at most 8 waves per workgroup");
     constexpr bool FULL = MODE != kModeAuto;
     constexpr int kDW = FULL ? 1 : 2;   // lines per diagonal run found
@@ -808,22 +811,33 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
     const int n = j.n, wp = j.wp, H = j.H, tau = j.tau;   // n: rows
     const int nb = FULL ? j.nb : n;                        // columns
     const int64_t band = j.theiler;                        // full matrix: cells |i-j| < band are 0
+    // Work item: a strip (auto), or a (strip, column segment) block (full).
+    const int strip = FULL ? item / j.segs : item;
+    const int seg = FULL ? item - strip * j.segs : 0;
     const int R0 = strip * H;
     const int R = R0 + 64 * wave;
     const int i = R + lane;                      // this lane's row
     const int c0 = FULL ? 0 : (R0 + wp) >> 6;
     const int T = j.c_last - c0 + 1;             // tiles of the strip
+    // Tiles [ta, tb) of this item; a full-matrix block that does not start at
+    // the left border begins with open diagonal runs of unknown history.
+    const int ta = FULL ? seg * j.seg_tiles : 0;
+    const int tb = FULL ? (ta + j.seg_tiles < T ? ta + j.seg_tiles : T) : T;
+    const bool seg_start = FULL && ta > 0;
     // Some row of this wave has cells to walk, and the first tile that has.
     const bool wave_has_u = FULL ? R <= n - 1 : R + wp <= n - 1;
     const int cfirst = FULL ? 0 : (R + wp) >> 6;
     const int64_t soff = FULL ? 0 : strip_offset(strip, n, wp, H);
     // Summary slots: auto -- per (strip, column / diagonal of U) in triangular
-    // strip order; full -- per strip nb columns and nb+H-1 diagonals
-    // k = -(R0+H-1) .. nb-1-R0.
+    // strip order; full -- per strip nb columns, and per (strip, segment)
+    // block j.dw diagonals k = x0-(R0+H-1) .. x1-1-R0 (the diagonals with a
+    // cell in the block's columns [x0, x1)).
+    const int x0 = (c0 + ta) * 64;
+    const int x1 = FULL ? ((c0 + tb) * 64 < nb ? (c0 + tb) * 64 : nb) : n;
     const int64_t vbase = FULL ? (int64_t)strip * nb : soff - R0 - wp;
-    const int64_t dbase = FULL ? (int64_t)strip * (nb + H - 1) + (R0 + H - 1) : soff - wp;
+    const int64_t dbase = FULL ? (int64_t)item * j.dw + (R0 + H - 1) - x0 : soff - wp;
     auto dok = [&](int k) -> bool {
-        return FULL ? (k >= -(R0 + H - 1) && k <= nb - 1 - R0) : (k >= wp && k <= n - 1 - R0);
+        return FULL ? (k >= x0 - (R0 + H - 1) && k <= x1 - 1 - R0) : (k >= wp && k <= n - 1 - R0);
     };
 
     // Column boxes of this job, when the probe chose to use them.
@@ -860,7 +874,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
     // wave w-1 wrote for the same tile and writes its own for wave w+1, through a
     // ring of kRing slots per wave pair.  A wave waits only for its neighbours:
     // for the tile's carries from above and for a free slot below.
-    const int tfirst = cfirst - c0;              // first tile with cells for this wave
+    const int tfirst = cfirst - c0 > ta ? cfirst - c0 : ta;   // first tile with cells for this wave
     if (wave > 0) publish_counter(&L.cons[wave - 1], wave_has_u ? tfirst : 0x7FFFFFFF);
     bool sync_ok = true;
     // Given matrix: the next tile's row word is loaded while the current tile
@@ -869,9 +883,9 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
     const auto mrow = MODE == kModeMatrix && i < n ? glb(j.bits) + (int64_t)i * j.words : nullptr;
     uint64_t mnext = 0;
     if constexpr (MODE == kModeMatrix) {
-        if (mrow && wave_has_u && tfirst < T) mnext = mrow[c0 + tfirst];
+        if (mrow && wave_has_u && tfirst < tb) mnext = mrow[c0 + tfirst];
     }
-    for (int t = wave_has_u ? tfirst : T; t < T; ++t) {
+    for (int t = wave_has_u ? tfirst : tb; t < tb; ++t) {
         const int c = c0 + t;
         const int slot = t & (kRing - 1);
         {
@@ -879,7 +893,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
             uint32_t xlo, xhi;
             if constexpr (MODE == kModeMatrix) {
                 const uint64_t word = mnext;
-                if (mrow && t + 1 < T) mnext = mrow[c + 1];
+                if (mrow && t + 1 < tb) mnext = mrow[c + 1];
                 xlo = (uint32_t)word;
                 xhi = (uint32_t)(word >> 32);
             } else {
@@ -932,6 +946,23 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
 
             const bool any = __ballot(X != 0ull) != 0ull;
 
+            // First tile of a full-matrix block that does not start at the left
+            // border: the diagonals entering through its left edge start a
+            // segment here.  Lane q's lower part (q > 0) begins at cell
+            // (R + 64 - q, jbase), bit 0 of lane 64 - q's row word; lane 0's
+            // lower part is empty and its diagonal enters the block in the wave
+            // below, which starts it (`fresh_up`).
+            const bool fresh = seg_start && t == ta;
+            if (fresh) {
+                const uint64_t col0 = __ballot((X & 1ull) != 0ull);
+                left = lane == 0 ? Run{0u, 0u, 0u}
+                                 : Run{(uint32_t)(col0 >> (64 - lane)) & 1u, 0u, 1u};
+            }
+            // The upper part of this lane's diagonal starts a segment in this
+            // tile: on the strip's top edge (wave 0), or for lane 0 on the
+            // block's left edge.
+            const bool fresh_up = wave == 0 || (fresh && lane == 0);
+
             // This tile's carries from the wave above, and a free slot below.
             // After one wait has given up the wave stops waiting (the job is
             // flagged as failed), so a strip finishes in bounded time.
@@ -977,7 +1008,7 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     const int kup = jbase + lane - R;
                     const int klo = kup - 64;
                     Run up;
-                    if (wave == 0) {
+                    if (fresh_up) {
                         if (!FULL || dok(kup)) *glb(j.dfirst + dbase + kup) = 0;   // white first cell
                         up = Run{0u, 0u, 0u};
                     } else {
@@ -1048,8 +1079,8 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                     const int klo = kup - 64;
                     const uint32_t nup = 64u - (uint32_t)lane;
                     Run up;
-                    if (wave == 0) {
-                        up = Run{1u, nup, 1u};   // black first run from the strip's top edge
+                    if (fresh_up) {
+                        up = Run{1u, nup, 1u};   // black first run from the block's edge
                     } else {
                         up = unpack_run(L.ds(slot, wave - 1, lane));
                         if (up.color) {
@@ -1144,11 +1175,11 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
                 const int klo = kup - 64;               // diagonal of the lower part
                 const uint64_t upwin = q == 0 ? ~0ull : ((1ull << (64 - q)) - 1ull);
                 Run up;
-                if (wave == 0) {
-                    // Segment start on the strip's top row.  A white first cell
-                    // means "no black run at the top edge": record it at once
-                    // (white diagonal runs are never counted, so their length
-                    // does not matter).
+                if (fresh_up) {
+                    // Segment start on the strip's top row (or the block's left
+                    // edge).  A white first cell means "no black run at the
+                    // edge": record it at once (white diagonal runs are never
+                    // counted, so their length does not matter).
                     up = Run{(uint32_t)(D & 1ull), 0u, 1u};
                     if (!up.color) {
                         if (dok(kup)) *glb(j.dfirst + dbase + kup) = 0;
@@ -1197,10 +1228,19 @@ __device__ void process_strip(const JobDesc &j, int strip, StripLds &L) {
         if constexpr (!FULL) {
             if (hstarted) finish_run<kHoriz>(hctx, hs.color, hs.len, hs.first);
         }
-        // Upper parts that left the last tile on its right edge end at the border.
-        const int kup = j.c_last * 64 + lane - R;
-        LineCtx lc{&j, bins, dbase + kup, dok(kup), 0u};
-        if (left.color || left.first) finish_run<kDiag, kDW>(lc, left.color, left.len, left.first);
+        // Upper parts that left the last tile on its right edge end at the
+        // border, and so do those whose next cell (one row down, in the next
+        // block) lies below the matrix; the others go on in the next block:
+        // recorded as the block's last runs.
+        const int kup = (c0 + tb - 1) * 64 + lane - R;
+        if (tb == T || R + 64 - lane > n - 1) {
+            LineCtx lc{&j, bins, dbase + kup, dok(kup), 0u};
+            if (left.color || left.first) finish_run<kDiag, kDW>(lc, left.color, left.len, left.first);
+        } else if (dok(kup)) {
+            const uint16_t b = (uint16_t)(left.color ? left.len : 0u);
+            *glb(j.dlast + dbase + kup) = b;
+            if (left.first) *glb(j.dfirst + dbase + kup) = b;
+        }
     }
 }
 
@@ -1344,18 +1384,33 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
         }
         emit_line(L, j, oc, ol);
     } else if (line < (int64_t)nb + n + nb - 1) {
+        // Diagonal k: its pieces in the (strip, segment) blocks it crosses, in
+        // order; a block's first and last black runs are folded across edges.
         const int k = (int)(line - nb) - (n - 1);
         const int r0 = k < 0 ? -k : 0;                              // first row
         const int r1 = n - 1 < nb - 1 - k ? n - 1 : nb - 1 - k;     // last row
-        const int sf = r0 / H, sl = r1 / H;
+        const int W = j.seg_tiles * 64;                             // segment width
         uint32_t open = 0;
-        for (int s = sf; s <= sl; ++s) {
-            const int64_t idx = (int64_t)s * (nb + H - 1) + (k + s * H + H - 1);
-            const bool top = s > sf || r0 == s * H;
-            const uint32_t fb = top ? (uint32_t)*glb(j.dfirst + idx) : 0u;
-            if (s < sl && top && fb == (uint32_t)H) { open += H; continue; }
-            if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 1u, (uint32_t)j.hmax, j.flag);
-            open = s < sl ? (uint32_t)*glb(j.dlast + idx) : 0u;
+        for (int s = r0 / H; s <= r1 / H; ++s) {
+            const int ra = r0 > s * H ? r0 : s * H;
+            const int rb = r1 < s * H + H - 1 ? r1 : s * H + H - 1;
+            const int ca = ra + k, cb = rb + k;                     // its columns in strip s
+            for (int g = ca / W; g <= cb / W; ++g) {
+                const int lo = ca > g * W ? ca : g * W;
+                const int hi = cb < g * W + W - 1 ? cb : g * W + W - 1;
+                const uint32_t len = (uint32_t)(hi - lo + 1);
+                const bool last = rb == r1 && hi == cb;
+                const int64_t idx = (int64_t)(s * j.segs + g) * j.dw + (s * H + H - 1 - g * W) + k;
+                // A piece that begins where the diagonal begins, below the
+                // strip's top row, starts at the matrix's left border: nothing
+                // enters it, and its runs were counted where they ended.
+                if (!(lo == ca && ra > s * H)) {
+                    const uint32_t fb = *glb(j.dfirst + idx);
+                    if (!last && fb == len) { open += len; continue; }
+                    if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 1u, (uint32_t)j.hmax, j.flag);
+                }
+                open = last ? 0u : (uint32_t)*glb(j.dlast + idx);
+            }
         }
     }
 }
@@ -1706,6 +1761,9 @@ int group_key(const Job &jb) {
 
 struct Layout {
     int H, nstrips;
+    int segs, seg_tiles;   // column segments per strip (full matrix; auto: 1) and their width
+    int items;             // work items: nstrips * segs
+    int dw;                // full matrix: diagonal summary slots per block
     int64_t ventries;      // vertical summary entries per array (first, last)
     int64_t dentries;      // diagonal summary entries per array
     int64_t tail_len;
@@ -1714,6 +1772,10 @@ struct Layout {
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Work items a full-matrix job is cut into (strips x column segments): a few
+// times the workgroups one launch keeps resident (256 CUs x 3).
+constexpr int kTargetItems = 2048;
 
 // Offset of the first evaluated diagonal of U, max(theiler, 1), clamped to n:
 // every window of n or more masks the whole matrix alike, and the clamp keeps
@@ -1741,12 +1803,29 @@ Layout layout_of(const Job &jb) {
         L.ventries = (int64_t)L.nstrips * (n - wp) -
                      (int64_t)L.H * ((int64_t)L.nstrips * (L.nstrips - 1) / 2);
         L.dentries = L.ventries;
+        L.segs = 1;
+        L.seg_tiles = n - wp > 0 ? (int)((n - 1) / 64 + 1) : 1;
+        L.dw = 0;
     } else {
+        // A strip of a full matrix walks every column tile; its chain of
+        // tiles is cut into column segments walked by different workgroups,
+        // enough of them for about kTargetItems work items, each at least
+        // max(8, H/64) tiles wide (so a diagonal crosses at most one segment
+        // edge inside a strip).
         const int64_t nb = jb.n_cols;
         L.nstrips = (int)((n + L.H - 1) / L.H);
+        const int T = (int)((nb - 1) / 64 + 1);
+        const int min_tiles = std::max(8, L.H / 64);
+        int segs = (int)std::min<int64_t>((kTargetItems + L.nstrips - 1) / L.nstrips,
+                                          std::max(1, T / min_tiles));
+        segs = std::max(segs, 1);
+        L.seg_tiles = (T + segs - 1) / segs;
+        L.segs = (T + L.seg_tiles - 1) / L.seg_tiles;
+        L.dw = L.seg_tiles * 64 + L.H - 1;
         L.ventries = (int64_t)L.nstrips * nb;
-        L.dentries = (int64_t)L.nstrips * (nb + L.H - 1);
+        L.dentries = (int64_t)L.nstrips * L.segs * L.dw;
     }
+    L.items = L.nstrips * L.segs;
     if (L.ventries < 1) L.ventries = 1;
     if (L.dentries < 1) L.dentries = 1;
     L.tail_len = jb.mode == kModeMatrix ? 0 : 64 + (int64_t)(jb.kp.m - 1) * jb.kp.tau;
@@ -1809,6 +1888,9 @@ JobDesc make_desc(const Job &jb, const Layout &lay, int strip_base, int stitch_b
     d.thr0 = kp.d0_bound;
     d.H = lay.H;
     d.nstrips = lay.nstrips;
+    d.segs = lay.segs;
+    d.seg_tiles = lay.seg_tiles;
+    d.dw = lay.dw;
     d.c_last = (int32_t)((ncols - 1) / 64);
     d.tail_len = (int32_t)lay.tail_len;
     d.strip_base = strip_base;
@@ -1943,7 +2025,7 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
         JobDesc d = make_desc(jb, lay, strip_acc, stitch_blocks);
         stat_grid = std::max(stat_grid, (int)d.stat_blocks);
         box_grid = std::max(box_grid, box_blocks_of(lay));
-        strip_acc += lay.nstrips;
+        strip_acc += lay.items;
         stitch_blocks += stitch_blocks_of(jb);
         hdesc[r] = d;
     }
@@ -2029,20 +2111,20 @@ int engine_launch_static(Job jb, void *scratch, hipStream_t st) {
     jb.scratch = base + engine_launch_scratch_bytes(1) + a256(kInfoBytes);
     const Layout lay = layout_of(jb);
     const JobDesc d = make_desc(jb, lay, 0, 0);
-    const GroupDesc g{0, 1, lay.nstrips, 0};
+    const GroupDesc g{0, 1, lay.items, 0};
     hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, d, g, ddesc, dgroups);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, st, ddesc, 1, dcounters, 64);
     hipLaunchKernelGGL(k_prepare, dim3(64, 1), dim3(256), 0, st, ddesc);
     hipLaunchKernelGGL(k_box_bounds, dim3(box_blocks_of(lay), 1), dim3(256), 0, st, ddesc);
     hipLaunchKernelGGL(k_box_probe, dim3(1), dim3(kProbeThreads), 0, st, ddesc);
-    if (lay.nstrips > 0) {
+    if (lay.items > 0) {
         TileKernel kern = tile_kernel(kModeAuto, jb.kp.norm, jb.kp.m);
         int occ = 0;
         const size_t lds = strip_lds_bytes(jb.waves);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * jb.waves, lds) != hipSuccess ||
             occ < 1)
             occ = 1;
-        const int grid = std::min(ncu * occ, lay.nstrips);
+        const int grid = std::min(ncu * occ, lay.items);
         hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * jb.waves), lds, st, ddesc, dgroups, 0,
                            dcounters);
     }

@@ -193,3 +193,24 @@ def test_dense_full_matrices(w, cuda, oracle_lib):
         res = comp.matrix(torch.from_numpy(bits.view(np.int64)).to(cuda), nc)
         comp.close()
         assert_same(res, ref_h, ref_m, tag=f"dense matrix w={w} waves {waves}")
+
+
+@pytest.mark.parametrize("waves", [1, 4, 8])
+def test_diagonals_across_column_segments(waves, cuda, oracle_lib):
+    """Long diagonal lines that cross the column-segment edges of the full-matrix
+    blocks (and the strip edges) at every offset: two copies of one slow,
+    slightly noisy sine, the second shifted and longer, so that the cross matrix
+    holds diagonal runs hundreds of cells long on many diagonals, together
+    with runs that end exactly at segment edges."""
+    rng = np.random.default_rng(81)
+    t = np.arange(9000)
+    base = np.sin(2 * np.pi * t / 377.0) + 0.02 * rng.normal(size=len(t))
+    a = base[:6100].astype(np.float32)
+    b = base[37:9000].astype(np.float32)
+    for norm, eps in ((3, 0.08), (2, 0.1)):
+        p = Params(m=2, tau=3, eps=eps, norm=norm, theiler=0)
+        _announce("cross-segments", waves=waves, norm=norm, na=len(a), nb=len(b))
+        ref = oracle_lib.cross_rqa(a, b, p)
+        assert_same(gpu_cross(a, b, p, cuda, waves=waves), *ref, tag=f"segments w{waves} n{norm}")
+        ref = oracle_lib.cross_rqa(b, a, p)
+        assert_same(gpu_cross(b, a, p, cuda, waves=waves), *ref, tag=f"segments T w{waves} n{norm}")
