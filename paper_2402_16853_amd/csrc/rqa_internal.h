@@ -69,6 +69,9 @@ struct Job {
     int64_t hist_stride = 0;        // entries from one histogram to the next (0: hist_len())
     KParams kp{};                   // parameters of this job
     int waves = 0;                  // waves per workgroup (strip height 64*waves), > 0
+    int segs = 0;                   // auto mode: column segments per strip (0: the engine
+                                    // decides, 1 for a job launched with others); scratch
+                                    // is sized for the largest choice
     // Histogram entries (index = line length, 0 unused): longest line + 1.
     int64_t hist_len() const {
         return (mode == kModeAuto ? n_vec : (n_cols > n_vec ? n_cols : n_vec)) + 1;

@@ -63,6 +63,7 @@ extern "C" int rqa_run_static(const rqa_params *p, const float *d_series, int64_
     jb.n_cols = nv;
     jb.kp = make_kparams(*p);
     jb.waves = engine_default_waves(nv);
+    jb.segs = 1;   // whole strips: the least scratch
     jb.hist = d_hist;
     jb.hist_stride = hist_len;
     jb.flag = reinterpret_cast<int *>(d_flag);

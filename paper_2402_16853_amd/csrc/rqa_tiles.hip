@@ -119,6 +119,8 @@ struct JobDesc {
     unsigned long long *hw;
     int *flag;                 // non-finite flag
     uint32_t *lead;            // leading run of each row of U: len | color<<31
+    uint32_t *hfirst;          // auto, segments > 1: per (row, segment) first / last run of
+    uint32_t *hlast;           // the row's piece in the segment, len | color<<31
     uint16_t *vfirst;          // per (strip, column): first run len | color<<15
     uint16_t *vlast;           // per (strip, column): last run len | color<<15
     uint16_t *dfirst;          // per (strip, diagonal): black run at the top edge
@@ -133,9 +135,12 @@ struct JobDesc {
     float thr0;                // first-coordinate bound (KParams::d0_bound)
     int32_t H;                 // strip height
     int32_t nstrips;
-    int32_t segs;              // full matrix: column segments per strip (auto: 1)
-    int32_t seg_tiles;         // column tiles per segment (>= H/64 and >= 8)
-    int32_t dw;                // full matrix: diagonal summary slots per (strip, segment) block
+    int32_t segs;              // column segments per strip (1: strips are not cut)
+    int32_t seg_tiles;         // column tiles per segment; segment g covers the column
+                               // tiles [seg_base + g*seg_tiles, seg_base + (g+1)*seg_tiles)
+    int32_t seg_base;          // first column tile of segment 0 (auto: wp/64; full: 0)
+    int32_t dw;                // diagonal summary slots per (strip, segment) block (segs > 1
+                               // or full matrix)
     int32_t c_last;            // last column tile (nb-1)/64
     int32_t tail_len;          // floats in tail
     int32_t strip_base;        // first work item of this job within its group
@@ -309,9 +314,10 @@ __device__ __forceinline__ void finish_run(const LineCtx &lc, uint32_t c, uint32
         else
             emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
     } else {
-        if (first)
-            *glb(j.lead + lc.row) = len | (c << 31);
-        else if (c)
+        if (first) {
+            if (lc.sum_ok) *glb(j.hfirst + lc.sum_idx) = len | (c << 31);   // a row piece
+            else *glb(j.lead + lc.row) = len | (c << 31);
+        } else if (c)
             emit(lc.bins.v, kCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
         else
             emit(lc.bins.w, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
@@ -811,34 +817,42 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     const int n = j.n, wp = j.wp, H = j.H, tau = j.tau;   // n: rows
     const int nb = FULL ? j.nb : n;                        // columns
     const int64_t band = j.theiler;                        // full matrix: cells |i-j| < band are 0
-    // Work item: a strip (auto), or a (strip, column segment) block (full).
-    const int strip = FULL ? item / j.segs : item;
-    const int seg = FULL ? item - strip * j.segs : 0;
+    // Work item: a (strip, column segment) block; with one segment per strip
+    // (auto mode, many strips) the whole strip.
+    const int G = j.segs;
+    const bool BLK = FULL || G > 1;              // per-block diagonal summaries
+    const int strip = item / G;
+    const int seg = item - strip * G;
     const int R0 = strip * H;
     const int R = R0 + 64 * wave;
     const int i = R + lane;                      // this lane's row
     const int c0 = FULL ? 0 : (R0 + wp) >> 6;
     const int T = j.c_last - c0 + 1;             // tiles of the strip
-    // Tiles [ta, tb) of this item; a full-matrix block that does not start at
-    // the left border begins with open diagonal runs of unknown history.
-    const int ta = FULL ? seg * j.seg_tiles : 0;
-    const int tb = FULL ? (ta + j.seg_tiles < T ? ta + j.seg_tiles : T) : T;
-    const bool seg_start = FULL && ta > 0;
+    // Tiles [ta, tb) of this block (relative to c0): the segment's absolute
+    // column tiles cut to the strip's.  A block that does not start at the
+    // strip's first tile begins with the row and diagonal runs that enter
+    // through its left edge, of unknown history.
+    const int sa = j.seg_base + seg * j.seg_tiles - c0;
+    const int ta = sa > 0 ? sa : 0;
+    const int tb = sa + j.seg_tiles < T ? sa + j.seg_tiles : T;
+    if (ta >= tb) return;                        // the triangle leaves this block empty
+    const bool seg_start = ta > 0;
     // Some row of this wave has cells to walk, and the first tile that has.
     const bool wave_has_u = FULL ? R <= n - 1 : R + wp <= n - 1;
     const int cfirst = FULL ? 0 : (R + wp) >> 6;
     const int64_t soff = FULL ? 0 : strip_offset(strip, n, wp, H);
-    // Summary slots: auto -- per (strip, column / diagonal of U) in triangular
-    // strip order; full -- per strip nb columns, and per (strip, segment)
-    // block j.dw diagonals k = x0-(R0+H-1) .. x1-1-R0 (the diagonals with a
-    // cell in the block's columns [x0, x1)).
+    // Summary slots: columns -- per (strip, column), in triangular strip order
+    // in auto mode; diagonals -- auto with one segment: per (strip, diagonal of
+    // U) in triangular strip order; otherwise per (strip, segment) block j.dw
+    // slots for the diagonals k = x0-(R0+H-1) .. x1-1-R0 that have a cell in
+    // the block's columns [x0, x1).
     const int x0 = (c0 + ta) * 64;
-    const int x1 = FULL ? ((c0 + tb) * 64 < nb ? (c0 + tb) * 64 : nb) : n;
+    const int x1 = (c0 + tb) * 64 < nb ? (c0 + tb) * 64 : nb;
     const int64_t vbase = FULL ? (int64_t)strip * nb : soff - R0 - wp;
-    const int64_t dbase = FULL ? (int64_t)item * j.dw + (R0 + H - 1) - x0 : soff - wp;
-    auto dok = [&](int k) -> bool {
-        return FULL ? (k >= x0 - (R0 + H - 1) && k <= x1 - 1 - R0) : (k >= wp && k <= n - 1 - R0);
-    };
+    const int64_t dbase = BLK ? (int64_t)item * j.dw + (R0 + H - 1) - x0 : soff - wp;
+    const int kmin = BLK ? (FULL || x0 - (R0 + H - 1) > wp ? x0 - (R0 + H - 1) : wp) : wp;
+    const int kmax = BLK ? x1 - 1 - R0 : n - 1 - R0;
+    auto dok = [&](int k) -> bool { return k >= kmin && k <= kmax; };
 
     // Column boxes of this job, when the probe chose to use them.
     // (The header is read as a scalar load, so `box` is known to be uniform
@@ -865,7 +879,10 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     }
 
     Bins bins{L.bd, L.bv, L.bw};
-    const LineCtx hctx{&j, bins, 0, false, (uint32_t)i};
+    // Horizontal runs: with segments, each row's piece in this block records
+    // its first and last runs (hfirst / hlast); otherwise the row's first run
+    // is its lead.
+    const LineCtx hctx{&j, bins, (int64_t)i * G + seg, G > 1, (uint32_t)i};
     Run hs{0, 0, 0};          // horizontal run of this lane's row (auto)
     bool hstarted = false;
     Run left{0, 0, 0};        // diagonal carry from the previous tile (upper part end)
@@ -957,6 +974,13 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                 const uint64_t col0 = __ballot((X & 1ull) != 0ull);
                 left = lane == 0 ? Run{0u, 0u, 0u}
                                  : Run{(uint32_t)(col0 >> (64 - lane)) & 1u, 0u, 1u};
+                // A row of U that began left of this block enters it here.
+                if constexpr (!FULL) {
+                    if (i < n && i + wp < jbase) {
+                        hs = Run{(uint32_t)(X & 1ull), 0u, 1u};
+                        hstarted = true;
+                    }
+                }
             }
             // The upper part of this lane's diagonal starts a segment in this
             // tile: on the strip's top edge (wave 0), or for lane 0 on the
@@ -1224,9 +1248,18 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     if (!sync_ok) g_or(j.flag, 8);   // a neighbour wait gave up: result invalid
 
     if (wave_has_u) {
-        // Rows end at column n-1: their last run is complete.
+        // Rows end at column n-1: their last run is complete; a block that is
+        // not the strip's last records each row's open run as its last.
         if constexpr (!FULL) {
-            if (hstarted) finish_run<kHoriz>(hctx, hs.color, hs.len, hs.first);
+            if (hstarted) {
+                if (tb == T) {
+                    finish_run<kHoriz>(hctx, hs.color, hs.len, hs.first);
+                } else {
+                    const uint32_t h = hs.len | (hs.color << 31);
+                    *glb(j.hlast + hctx.sum_idx) = h;
+                    if (hs.first) *glb(j.hfirst + hctx.sum_idx) = h;
+                }
+            }
         }
         // Upper parts that left the last tile on its right edge end at the
         // border, and so do those whose next cell (one row down, in the next
@@ -1344,6 +1377,60 @@ __device__ __forceinline__ void emit_line(StitchLds &L, const JobDesc &j, uint32
     if (len == 0) return;
     if (color) emit_stitch(L.bv, kStitchCapV, j.hv, len, 1u, (uint32_t)j.hmax, j.flag);
     else emit_stitch(L.bw, kCapW, j.hw, len, 1u, (uint32_t)j.hmax, j.flag);
+}
+
+// Segment of column x (a column of segment g lies in the column tiles
+// [seg_base + g*seg_tiles, seg_base + (g+1)*seg_tiles)).
+__device__ __forceinline__ int seg_of(const JobDesc &j, int x) {
+    return ((x >> 6) - j.seg_base) / j.seg_tiles;
+}
+
+// Row r of U, cut into pieces by the column segments (auto mode, segs > 1):
+// fold the pieces' first and last runs in order, count the runs that span
+// piece edges and return the row's first (leading) run, which the join with
+// column r needs.  Runs inside a piece were counted by the tile kernel, and so
+// was the last piece's final run at column n-1 unless it is that piece's
+// first.
+__device__ void row_pieces(StitchLds &L, const JobDesc &j, int r, uint32_t &lc, uint32_t &ll) {
+    const int n = j.n;
+    const int a = r + j.wp;                     // first column of the row
+    const int W = j.seg_tiles * 64;
+    bool lead_open = true, have = false;
+    uint32_t oc = 0, ol = 0;
+    lc = 0;
+    ll = 0;
+    auto close = [&](uint32_t c, uint32_t l) {
+        if (lead_open) { lc = c; ll = l; lead_open = false; }
+        else emit_line(L, j, c, l);
+    };
+    const int gl = seg_of(j, n - 1);
+    for (int g = seg_of(j, a); g <= gl; ++g) {
+        const int g0 = (j.seg_base + g * j.seg_tiles) * 64;
+        const int lo = a > g0 ? a : g0;
+        const int hi = n - 1 < g0 + W - 1 ? n - 1 : g0 + W - 1;
+        const uint32_t len = (uint32_t)(hi - lo + 1);
+        const bool last = g == gl;
+        const int64_t idx = (int64_t)r * j.segs + g;
+        const uint32_t f = *glb(j.hfirst + idx);
+        const uint32_t fc = f >> 31, fl = f & 0x7FFFFFFFu;
+        if (have && fc == oc) {
+            ol += fl;
+        } else {
+            if (have) close(oc, ol);
+            oc = fc;
+            ol = fl;
+            have = true;
+        }
+        if (fl == len && !last) continue;       // the piece is one run: it stays open
+        close(oc, ol);                          // the open run ends in this piece
+        have = false;
+        if (!last) {
+            const uint32_t h = *glb(j.hlast + idx);
+            oc = h >> 31;
+            ol = h & 0x7FFFFFFFu;
+            have = true;
+        }
+    }
 }
 
 // Stitch of a full (not symmetric) matrix: lines [0, nb) are the columns, lines
@@ -1487,8 +1574,14 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
         if (ol && oc == mc) ol += ml;
         else { emit_line(L, j, oc, ol); oc = mc; ol = ml; }
         if (col + wp <= n - 1) {
-            const uint32_t ld = *glb(j.lead + col);
-            const uint32_t hc = ld >> 31, hl = ld & 0x7FFFFFFFu;
+            uint32_t hc, hl;
+            if (j.segs > 1) {
+                row_pieces(L, j, col, hc, hl);
+            } else {
+                const uint32_t ld = *glb(j.lead + col);
+                hc = ld >> 31;
+                hl = ld & 0x7FFFFFFFu;
+            }
             if (oc == hc) ol += hl;
             else { emit_line(L, j, oc, ol); oc = hc; ol = hl; }
         }
@@ -1496,7 +1589,30 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
     } else if (line < 2 * (int64_t)n) {
         // ---- diagonal k of U (and its mirror) ----
         const int k = (int)(line - n);
-        if (k >= wp) {
+        if (k >= wp && j.segs > 1) {
+            // its pieces in the (strip, segment) blocks it crosses, in order
+            const int r1 = n - 1 - k;
+            uint32_t open = 0;
+            for (int s = 0; s <= r1 / H; ++s) {
+                const int ra = s * H;
+                const int rb = r1 < s * H + H - 1 ? r1 : s * H + H - 1;
+                const int ca = ra + k, cb = rb + k;
+                const int xs = ((s * H + wp) >> 6) * 64;   // the strip's first column tile
+                for (int g = seg_of(j, ca); g <= seg_of(j, cb); ++g) {
+                    const int g0 = (j.seg_base + g * j.seg_tiles) * 64;
+                    const int lo = ca > g0 ? ca : g0;
+                    const int hi = cb < g0 + j.seg_tiles * 64 - 1 ? cb : g0 + j.seg_tiles * 64 - 1;
+                    const uint32_t len = (uint32_t)(hi - lo + 1);
+                    const bool last = rb == r1 && hi == cb;
+                    const int bx0 = g0 > xs ? g0 : xs;      // the block's first column
+                    const int64_t idx = (int64_t)(s * j.segs + g) * j.dw + (s * H + H - 1 - bx0) + k;
+                    const uint32_t fb = *glb(j.dfirst + idx);
+                    if (!last && fb == len) { open += len; continue; }
+                    if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
+                    open = last ? 0u : (uint32_t)*glb(j.dlast + idx);
+                }
+            }
+        } else if (k >= wp) {
             const int s_last = (n - 1 - k) / H;
             uint32_t open = 0;
             for (int s0 = 0; s0 <= s_last; s0 += kStitchBatch) {
@@ -1761,14 +1877,16 @@ int group_key(const Job &jb) {
 
 struct Layout {
     int H, nstrips;
-    int segs, seg_tiles;   // column segments per strip (full matrix; auto: 1) and their width
+    int segs, seg_tiles;   // column segments per strip and their width (tiles)
+    int seg_base;          // first column tile of segment 0
+    int64_t hentries;      // row pieces (auto, segs > 1): n * segs
     int items;             // work items: nstrips * segs
     int dw;                // full matrix: diagonal summary slots per block
     int64_t ventries;      // vertical summary entries per array (first, last)
     int64_t dentries;      // diagonal summary entries per array
     int64_t tail_len;
     int64_t box_floats;    // column boxes (header + records), 0 if none
-    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, off_box, bytes;
+    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, off_hf, off_hl, off_box, bytes;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1792,6 +1910,17 @@ int default_waves_impl(int64_t n) {
     return 4;
 }
 
+// Column segments of an auto-mode job when it runs alone: enough for about
+// kTargetItems work items, each at least 64 tiles wide; 1 for jobs whose
+// first strip is shorter than 128 tiles (their chains are short) or that
+// already have that many strips (the 1,048,576-point workload has 2,048).
+int auto_segs_max(int64_t n, int wp, int H) {
+    const int nstrips = n - wp > 0 ? (int)((n - wp + H - 1) / H) : 0;
+    const int T0 = (int)((n - 1) / 64 - wp / 64 + 1);
+    if (nstrips < 1 || T0 < 128) return 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((kTargetItems + nstrips - 1) / nstrips, T0 / 64));
+}
+
 Layout layout_of(const Job &jb) {
     Layout L{};
     const int64_t n = jb.n_vec;
@@ -1802,10 +1931,21 @@ Layout layout_of(const Job &jb) {
         // sum over strips of (n - wp - s H) entries
         L.ventries = (int64_t)L.nstrips * (n - wp) -
                      (int64_t)L.H * ((int64_t)L.nstrips * (L.nstrips - 1) / 2);
-        L.dentries = L.ventries;
-        L.segs = 1;
-        L.seg_tiles = n - wp > 0 ? (int)((n - 1) / 64 + 1) : 1;
-        L.dw = 0;
+        // Segments: as set on the job, else the most it could be given.
+        const int T0 = (int)((n - 1) / 64 - wp / 64 + 1);
+        int segs = jb.segs > 0 ? jb.segs : auto_segs_max(n, wp, L.H);
+        L.seg_base = wp / 64;
+        L.seg_tiles = (T0 + segs - 1) / segs;
+        L.segs = segs > 1 ? (T0 + L.seg_tiles - 1) / L.seg_tiles : 1;
+        if (L.segs > 1) {
+            L.dw = L.seg_tiles * 64 + L.H - 1;
+            L.dentries = (int64_t)L.nstrips * L.segs * L.dw;
+            L.hentries = n * L.segs;
+        } else {
+            L.dw = 0;
+            L.dentries = L.ventries;
+            L.hentries = 0;
+        }
     } else {
         // A strip of a full matrix walks every column tile; its chain of
         // tiles is cut into column segments walked by different workgroups,
@@ -1819,11 +1959,13 @@ Layout layout_of(const Job &jb) {
         int segs = (int)std::min<int64_t>((kTargetItems + L.nstrips - 1) / L.nstrips,
                                           std::max(1, T / min_tiles));
         segs = std::max(segs, 1);
+        L.seg_base = 0;
         L.seg_tiles = (T + segs - 1) / segs;
         L.segs = (T + L.seg_tiles - 1) / L.seg_tiles;
         L.dw = L.seg_tiles * 64 + L.H - 1;
         L.ventries = (int64_t)L.nstrips * nb;
         L.dentries = (int64_t)L.nstrips * L.segs * L.dw;
+        L.hentries = 0;
     }
     L.items = L.nstrips * L.segs;
     if (L.ventries < 1) L.ventries = 1;
@@ -1838,6 +1980,8 @@ Layout layout_of(const Job &jb) {
     L.off_df = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
     L.off_dl = off; off += a256(sizeof(uint16_t) * (size_t)L.dentries);
     L.off_ent = off; off += a256(sizeof(double) * 3 * kStatMaxBlocks);
+    L.off_hf = off; off += a256(sizeof(uint32_t) * (size_t)L.hentries);
+    L.off_hl = off; off += a256(sizeof(uint32_t) * (size_t)L.hentries);
     // Boxes for the modes with a predicate and the embedding dimensions whose
     // row coordinates live in registers.
     const int64_t ncols = jb.mode == kModeAuto ? n : jb.n_cols;
@@ -1890,7 +2034,10 @@ JobDesc make_desc(const Job &jb, const Layout &lay, int strip_base, int stitch_b
     d.nstrips = lay.nstrips;
     d.segs = lay.segs;
     d.seg_tiles = lay.seg_tiles;
+    d.seg_base = lay.seg_base;
     d.dw = lay.dw;
+    d.hfirst = lay.hentries > 0 ? reinterpret_cast<uint32_t *>(scr + lay.off_hf) : nullptr;
+    d.hlast = lay.hentries > 0 ? reinterpret_cast<uint32_t *>(scr + lay.off_hl) : nullptr;
     d.c_last = (int32_t)((ncols - 1) / 64);
     d.tail_len = (int32_t)lay.tail_len;
     d.strip_base = strip_base;
@@ -2010,7 +2157,10 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     int ngroups = 0;
     int strip_acc = 0;
     for (int r = 0; r < njobs; ++r) {
-        const Job &jb = jobs_in[order[r]];
+        // A job launched with others keeps whole strips: the launch has work
+        // items enough, and its scratch is sized for any choice.
+        Job jb = jobs_in[order[r]];
+        if (jb.segs == 0 && njobs > 1) jb.segs = 1;
         const Layout lay = layout_of(jb);
         const int key = group_key(jb);
         if (ngroups == 0 || gkeys.back() != key) {

@@ -181,3 +181,19 @@ def test_theiler_at_and_beyond_n(theiler, cuda, oracle_lib):
     for waves in (1, 8):
         _announce("theiler_large", theiler=w, n=n, waves=waves)
         assert_same(run_gpu(s, p, cuda, waves=waves), *ref, tag=f"theiler {w} waves {waves}")
+
+
+@pytest.mark.parametrize("waves", [1, 2, 8])
+def test_auto_column_segments(waves, cuda, oracle_lib):
+    """A job launched alone whose strips are long is cut into column segments
+    (blocks walked by different workgroups): rows of U, diagonals and their
+    mirrors cross the segment edges.  Lorenz and AR(1) series of 20,000-40,000
+    points, Theiler windows 0, 1 and 70, every norm."""
+    cases = [("lorenz", 30_000, 0), ("lorenz", 20_000, 70), ("ar1_season", 40_000, 1)]
+    for name, n, w in cases:
+        s, p = workload(name, seed=5, n=n)
+        for norm in (1, 2, 3):
+            q = Params(m=p.m, tau=p.tau, eps=p.eps, norm=norm, theiler=w)
+            _announce("auto_segments", name=name, n=n, w=w, norm=norm, waves=waves)
+            assert_same(run_gpu(s, q, cuda, waves=waves), *oracle_lib.rqa(s, q),
+                        tag=f"{name} n={n} w={w} norm={norm} waves={waves}")
