@@ -443,6 +443,61 @@ def bench_paper_e2(args, torch, RQA, workload):
     return out
 
 
+def bench_bands(args, torch, RQA, workload, hl):
+    """Recombination in bounded memory: the headline series with its line
+    summaries held to 1 GiB (row bands with per-line carries) next to the
+    one-band run, and a 4,194,304-point Lorenz-63 series with the default limit
+    (a quarter of the device's memory) and with 1 GiB.  Full RQA per run
+    (histograms and measures to the host), median of 3 after one warm run."""
+    dev = torch.device("cuda:0")
+
+    def timed(comp, ds, limit):
+        comp.set_workspace_limit(limit)
+        comp.run(ds)
+        comp.result(histograms=True)
+        t = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            comp.run(ds)
+            comp.result(histograms=True)
+            t.append(time.perf_counter() - t0)
+        return float(np.median(t)) * 1e3, comp.last_plan()
+
+    out = {}
+    s, p = hl["series"], hl["p"]
+    n = hl["n"]
+    ds = torch.from_numpy(s).to(dev)
+    comp = RQA.from_params(p)
+    comp.set_tiling(8, 0)
+    one_ms, one_plan = timed(comp, ds, 1 << 50)
+    ms, plan = timed(comp, ds, 1 << 30)
+    comp.close()
+    del ds
+    out["N1048576"] = {"limit_bytes": 1 << 30, "ms": round(ms, 2),
+                       "gcells_per_s": round(float(n) * n / (ms * 1e-3) / 1e9, 1), **plan,
+                       "one_band": {"ms": round(one_ms, 2), **one_plan}}
+    log(f"[bench] bands N=1M: 1 GiB {ms:.1f} ms ({plan['bands']} bands, "
+        f"{plan['workspace_bytes'] / 1e9:.2f} GB) vs one band {one_ms:.1f} ms "
+        f"({one_plan['workspace_bytes'] / 1e9:.2f} GB)")
+    s4, p4 = workload("lorenz", seed=args.seed, n=4_194_304)
+    n4 = len(s4) - (p4.m - 1) * p4.tau
+    ds = torch.from_numpy(s4).to(dev)
+    comp = RQA.from_params(p4)
+    comp.set_tiling(8, 0)
+    big = {"n_points": len(s4), "n_vec": n4, "eps": p4.eps}
+    for tag, limit in (("default_limit", 0), ("limit_1GiB", 1 << 30)):
+        ms, plan = timed(comp, ds, limit)
+        big[tag] = {"ms": round(ms, 1), "gcells_per_s": round(float(n4) * n4 / (ms * 1e-3) / 1e9, 1),
+                    **plan}
+        log(f"[bench] bands N=4M {tag}: {ms:.0f} ms ({plan['bands']} bands, "
+            f"{plan['workspace_bytes'] / 1e9:.2f} GB)")
+    comp.close()
+    del ds
+    out["N4194304"] = big
+    return out
+
+
 def default_waves(n_vec: int) -> int:
     """Waves per workgroup the server uses for a job of n_vec delay vectors
     (the library's default shape: 8 from 32,768 vectors, else 4)."""
@@ -600,7 +655,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--quick", action="store_true", help="headline only")
     ap.add_argument("--only", default="", help="comma list of extra phases to run after the "
-                    "headline: batched, served, full, e2, cpu (default: all)")
+                    "headline: batched, served, full, e2, bands, cpu (default: all)")
     ap.add_argument("--waves", type=int, default=0, help="waves per workgroup (0 = default)")
     ap.add_argument("--sweep", action="store_true", help="time the tile kernel per waves setting")
     ap.add_argument("--probe-valu", action="store_true",
@@ -664,6 +719,8 @@ def main():
         extra.update(bench_full_matrices(args, torch, RQA, workload))
     if want("e2", False):
         extra["paper_e2"] = bench_paper_e2(args, torch, RQA, workload)
+    if want("bands", False):
+        extra["bands"] = bench_bands(args, torch, RQA, workload, hl)
     cpu = None
     if want("cpu", args.no_cpu):
         cpu = bench_cpu_baseline(args, hl)

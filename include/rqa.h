@@ -223,6 +223,29 @@ int rqa_get_timings(rqa_handle *h, double *prepare_ms, double *tiles_ms, double 
  * RQA_ESTATE before the first run. */
 int rqa_last_launch(const rqa_handle *h, int32_t *waves, int32_t *graph_replay);
 
+/* Memory bound of the recombination (Sect. 4.1, Divide & Recombine: the matrix
+ * is processed in parts that fit the memory, and lines crossing their borders
+ * pass on through carry-over state).  A run of one series keeps, per strip of
+ * rows and line, the runs at the strip's edges until they are joined; for long
+ * series that is O(n^2 / strip height) bytes.  When that would exceed `bytes`,
+ * the run walks the strips in row bands: each band's tile kernel writes its
+ * edge runs, the band's stitch joins them into one open run per column and per
+ * diagonal (O(n) carries), and the next band reuses the space.  Results are
+ * identical (with several bands, the tile phase of rqa_get_timings also holds
+ * the stitch of every band but the last).  bytes = 0 restores the default: a
+ * quarter of the device's memory.  Applies to rqa_run (one series, or a batch of one window); batches
+ * of several windows, cross recurrence and given matrices are not banded.
+ * RQA_EINVAL for bytes < 0; a bound below what one band needs runs with one
+ * strip per band (and may then fail with RQA_ENOMEM). */
+int rqa_set_workspace_limit(rqa_handle *h, int64_t bytes);
+
+/* How the last run was cut: row bands and strips per band (1 and all strips
+ * when unbanded), column segments per strip, rows per strip, and the device
+ * workspace of its first job's line summaries in bytes.  Any output pointer
+ * may be NULL.  RQA_ESTATE before the first run. */
+int rqa_last_plan(const rqa_handle *h, int32_t *bands, int32_t *band_strips, int32_t *segs,
+                  int32_t *strip_rows, int64_t *workspace_bytes);
+
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * RQA as rqa_run + rqa_result of one device series under the parameters *p,

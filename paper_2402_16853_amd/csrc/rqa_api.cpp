@@ -153,6 +153,8 @@ struct rqa_handle {
     PhaseEvents prof{};
     int waves = 0;                  // 0 = autotuned
     int groups = 0;                 // 0 = fill the device
+    int64_t ws_limit = 0;           // line-summary bytes of a one-series run (0 = default)
+    JobPlan plan{};                 // how the last run's first job was cut
     bool has_run = false;
     bool batched = false;
     hipStream_t stream = nullptr;
@@ -257,8 +259,25 @@ int launch(rqa_handle *h, std::vector<Job> &jobs, int waves, bool trial, const s
     const size_t info_block_off = total;
     total += align256(kInfoBytes * static_cast<size_t>(count));
     const size_t hist_block_off = total;
+    for (int32_t w = 0; w < count; ++w) jobs[w].waves = waves;
+    // A series run alone is cut into row bands when its line summaries would
+    // exceed the workspace limit.
+    if (count == 1 && jobs[0].mode == kModeAuto) {
+        size_t limit = static_cast<size_t>(h->ws_limit);
+        if (limit == 0) {
+            int dev = 0;
+            size_t total_mem = 0;
+            if (hipGetDevice(&dev) != hipSuccess || hipDeviceTotalMem(&total_mem, dev) != hipSuccess)
+                return RQA_EDEVICE;
+            limit = total_mem / 4;
+        }
+        jobs[0].band_strips = engine_band_strips(jobs[0], limit);
+        sig = fnv(sig, &jobs[0].band_strips, sizeof jobs[0].band_strips);
+    }
+    Job first = jobs[0];
+    if (count > 1 && first.segs == 0) first.segs = 1;   // as the engine launches it
+    const JobPlan plan = engine_job_plan(first);
     for (int32_t w = 0; w < count; ++w) {
-        jobs[w].waves = waves;
         nvec[w] = jobs[w].n_vec;
         ncols[w] = jobs[w].mode == kModeAuto ? jobs[w].n_vec : jobs[w].n_cols;
         hlen[w] = jobs[w].hist_len();
@@ -323,6 +342,7 @@ int launch(rqa_handle *h, std::vector<Job> &jobs, int waves, bool trial, const s
         if (rc != RQA_OK) return rc;
     }
     h->last_sig = sig;
+    h->plan = plan;
     h->trial = trial;
     h->trial_waves = waves;
     h->trial_key = key;
@@ -717,6 +737,24 @@ int rqa_last_launch(const rqa_handle *h, int32_t *waves, int32_t *graph_replay) 
     if (!h->has_run) return RQA_ESTATE;
     if (waves) *waves = h->trial_waves;
     if (graph_replay) *graph_replay = h->last_from_graph ? 1 : 0;
+    return RQA_OK;
+}
+
+int rqa_set_workspace_limit(rqa_handle *h, int64_t bytes) {
+    if (!h || bytes < 0) return RQA_EINVAL;
+    h->ws_limit = bytes;
+    return RQA_OK;
+}
+
+int rqa_last_plan(const rqa_handle *h, int32_t *bands, int32_t *band_strips, int32_t *segs,
+                  int32_t *strip_rows, int64_t *workspace_bytes) {
+    if (!h) return RQA_EINVAL;
+    if (!h->has_run) return RQA_ESTATE;
+    if (bands) *bands = h->plan.bands;
+    if (band_strips) *band_strips = h->plan.band_strips;
+    if (segs) *segs = h->plan.segs;
+    if (strip_rows) *strip_rows = h->plan.strip_rows;
+    if (workspace_bytes) *workspace_bytes = static_cast<int64_t>(h->plan.scratch_bytes);
     return RQA_OK;
 }
 

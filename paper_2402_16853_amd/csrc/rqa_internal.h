@@ -72,6 +72,10 @@ struct Job {
     int segs = 0;                   // auto mode: column segments per strip (0: the engine
                                     // decides, 1 for a job launched with others); scratch
                                     // is sized for the largest choice
+    int band_strips = 0;            // auto mode, a job launched alone: strips per row
+                                    // band (0: one band).  The strip-edge summaries then
+                                    // hold one band's strips and per-line carries pass
+                                    // the open runs from band to band
     // Histogram entries (index = line length, 0 unused): longest line + 1.
     int64_t hist_len() const {
         return (mode == kModeAuto ? n_vec : (n_cols > n_vec ? n_cols : n_vec)) + 1;
@@ -92,6 +96,20 @@ struct Workspace {
 // descriptors and the work counter) of a launch over `njobs` jobs.
 size_t engine_job_scratch_bytes(const Job &job);
 size_t engine_launch_scratch_bytes(size_t njobs);
+
+// Row bands for a job (auto mode) launched alone whose scratch would exceed
+// `limit` bytes: the largest number of strips per band whose scratch fits, at
+// least 1; 0 when the job fits in one band or `limit` is 0.  The job's waves
+// (strip height) must be set.
+int engine_band_strips(const Job &job, size_t limit);
+
+// How a launch of `job` alone is cut: row bands, strips per band, column
+// segments per strip, strip height, and the job's scratch bytes.
+struct JobPlan {
+    int bands, band_strips, segs, strip_rows;
+    size_t scratch_bytes;
+};
+JobPlan engine_job_plan(const Job &job);
 
 // Default waves per workgroup for a job of n delay vectors.
 int engine_default_waves(int64_t n);

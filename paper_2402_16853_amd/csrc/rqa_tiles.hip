@@ -153,6 +153,15 @@ struct JobDesc {
     int32_t spin_limit;        // polls before a neighbour wait gives up (kSpinLimit)
     int32_t wait_bias;         // added to every wait target: 0, or (fault injection
                                // for tests) a bias no counter reaches
+    // Row bands (auto mode): the launch walks strips [s_lo, s_hi) of band_strips
+    // per band; summary slots are relative to strip s_lo (strip_offset(s_lo) =
+    // soff_lo).  With several bands the open run of each column of U and of
+    // each diagonal passes to the next band through cstate / dstate.
+    int32_t s_lo, s_hi;
+    int32_t band_strips, nbands;
+    int64_t soff_lo;
+    uint32_t *cstate;          // per column: open run len | color<<31 (nbands > 1)
+    uint32_t *dstate;          // per diagonal: open black run length (nbands > 1)
 };
 
 struct GroupDesc {
@@ -742,6 +751,21 @@ __global__ void k_setup(const JobDesc d, const GroupDesc g, JobDesc *ddesc, Grou
     }
 }
 
+// Move a one-job launch to row band b: its strips [b K, min((b+1) K, S)), the
+// origin of their summary slots, the band's work items, and a fresh work
+// counter (K strips per band, S strips in all).
+__global__ void k_band(JobDesc *jobs, GroupDesc *groups, int *counters, int b) {
+    if (threadIdx.x != 0) return;
+    JobDesc &j = jobs[0];
+    const int lo = b * j.band_strips;
+    const int hi = lo + j.band_strips < j.nstrips ? lo + j.band_strips : j.nstrips;
+    j.s_lo = lo;
+    j.s_hi = hi;
+    j.soff_lo = strip_offset(lo, j.n, j.wp, j.H);
+    groups[0].items = (hi - lo) * j.segs;
+    counters[0] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Kernel 2: the fused tile pass.  Persistent workgroups pull (job, strip) work
 // items of one (norm, m) group from a counter.
@@ -821,8 +845,9 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     // (auto mode, many strips) the whole strip.
     const int G = j.segs;
     const bool BLK = FULL || G > 1;              // per-block diagonal summaries
-    const int strip = item / G;
-    const int seg = item - strip * G;
+    const int lstrip = item / G;                 // strip within the row band (auto)
+    const int strip = (FULL ? 0 : j.s_lo) + lstrip;
+    const int seg = item - lstrip * G;
     const int R0 = strip * H;
     const int R = R0 + 64 * wave;
     const int i = R + lane;                      // this lane's row
@@ -840,12 +865,12 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     // Some row of this wave has cells to walk, and the first tile that has.
     const bool wave_has_u = FULL ? R <= n - 1 : R + wp <= n - 1;
     const int cfirst = FULL ? 0 : (R + wp) >> 6;
-    const int64_t soff = FULL ? 0 : strip_offset(strip, n, wp, H);
+    const int64_t soff = FULL ? 0 : strip_offset(strip, n, wp, H) - j.soff_lo;
     // Summary slots: columns -- per (strip, column), in triangular strip order
-    // in auto mode; diagonals -- auto with one segment: per (strip, diagonal of
-    // U) in triangular strip order; otherwise per (strip, segment) block j.dw
-    // slots for the diagonals k = x0-(R0+H-1) .. x1-1-R0 that have a cell in
-    // the block's columns [x0, x1).
+    // from the row band's first strip in auto mode; diagonals -- auto with one
+    // segment: per (strip, diagonal of U) in the same order; otherwise per
+    // work item (a (strip, segment) block) j.dw slots for the diagonals
+    // k = x0-(R0+H-1) .. x1-1-R0 that have a cell in the block's columns [x0, x1).
     const int x0 = (c0 + ta) * 64;
     const int x1 = (c0 + tb) * 64 < nb ? (c0 + tb) * 64 : nb;
     const int64_t vbase = FULL ? (int64_t)strip * nb : soff - R0 - wp;
@@ -882,7 +907,7 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     // Horizontal runs: with segments, each row's piece in this block records
     // its first and last runs (hfirst / hlast); otherwise the row's first run
     // is its lead.
-    const LineCtx hctx{&j, bins, (int64_t)i * G + seg, G > 1, (uint32_t)i};
+    const LineCtx hctx{&j, bins, (int64_t)(i - (FULL ? 0 : j.s_lo) * H) * G + seg, G > 1, (uint32_t)i};
     Run hs{0, 0, 0};          // horizontal run of this lane's row (auto)
     bool hstarted = false;
     Run left{0, 0, 0};        // diagonal carry from the previous tile (upper part end)
@@ -1410,7 +1435,7 @@ __device__ void row_pieces(StitchLds &L, const JobDesc &j, int r, uint32_t &lc, 
         const int hi = n - 1 < g0 + W - 1 ? n - 1 : g0 + W - 1;
         const uint32_t len = (uint32_t)(hi - lo + 1);
         const bool last = g == gl;
-        const int64_t idx = (int64_t)r * j.segs + g;
+        const int64_t idx = (int64_t)(r - j.s_lo * j.H) * j.segs + g;   // rows of the band
         const uint32_t f = *glb(j.hfirst + idx);
         const uint32_t fc = f >> 31, fl = f & 0x7FFFFFFFu;
         if (have && fc == oc) {
@@ -1436,7 +1461,7 @@ __device__ void row_pieces(StitchLds &L, const JobDesc &j, int r, uint32_t &lc, 
 // Stitch of a full (not symmetric) matrix: lines [0, nb) are the columns, lines
 // [nb, nb + n + nb - 1) the diagonals k = -(n-1) .. nb-1.  A diagonal that
 // starts inside a strip (at the left border) has no top-edge summary there.
-__device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
+__device__ __forceinline__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
     const int n = j.n, nb = j.nb, H = j.H, S = j.nstrips;
     if (line < nb) {
         const int col = (int)line;
@@ -1502,6 +1527,155 @@ __device__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
     }
 }
 
+// Stitch of the recurrence matrix of one series over the strips [s_lo, s_hi)
+// of one row band (all strips when the job has one band).  Lines of the band:
+// the columns [s_lo H, n), then the diagonals k = 0 .. n-1-s_lo H; the other
+// lines have no piece in these strips.  A line whose pieces go on in a later
+// band keeps its open run in cstate / dstate; column col joins the band and
+// row col of U in the band that holds that row (its lead, or its pieces).
+__device__ __forceinline__ void stitch_auto(StitchLds &L, const JobDesc &j, int64_t line) {
+    const int n = j.n, wp = j.wp, H = j.H;
+    const int s_lo = j.s_lo, s_hi = j.s_hi;
+    const bool last_band = s_hi >= j.nstrips;
+    const bool carried = j.nbands > 1 && s_lo > 0;   // open runs come from earlier bands
+    const int64_t lines = (int64_t)n - (int64_t)s_lo * H;
+    if (line < lines) {
+        // ---- column col of the full matrix ----
+        const int col = (int)((int64_t)s_lo * H + line);
+        const int s_last = col >= wp ? (col - wp) / H : -1;   // strips holding column col of U
+        const bool has_row = col + wp <= n - 1;               // row col of U has cells
+        const int js = has_row ? col / H : (s_last > 0 ? s_last : 0);
+        const bool join = js >= s_lo && (js < s_hi || last_band);
+        const int sb = s_last < s_hi - 1 ? s_last : s_hi - 1;   // last strip folded here
+        uint32_t oc = 0, ol = 0;   // open run after folding column `col` of U
+        if (carried && s_last >= 0 && (join || sb >= s_lo)) {
+            const uint32_t c = *glb(j.cstate + col);
+            oc = c >> 31;
+            ol = c & 0x7FFFFFFFu;
+        }
+        // The summaries of kStitchBatch strips are loaded before any is
+        // folded, so a thread has that many loads in flight.
+        for (int s0 = s_lo; s0 <= sb; s0 += kStitchBatch) {
+            uint32_t fv[kStitchBatch], lv[kStitchBatch];
+#pragma unroll
+            for (int u = 0; u < kStitchBatch; ++u) {
+                const int s = s0 + u;
+                if (s <= sb) {
+                    const int64_t idx = strip_offset(s, n, wp, H) - j.soff_lo + (col - s * H - wp);
+                    fv[u] = *glb(j.vfirst + idx);
+                    lv[u] = *glb(j.vlast + idx);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStitchBatch; ++u) {
+                const int s = s0 + u;
+                if (s > sb) break;
+                const uint32_t Ls = s < s_last ? (uint32_t)H : (uint32_t)(col - wp - s * H + 1);
+                const uint32_t f = fv[u], l = lv[u];
+                const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
+                if (fl == Ls) {   // the segment is one run
+                    if (ol && oc == fc) ol += Ls;
+                    else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
+                } else {
+                    if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
+                    else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
+                    oc = l >> 15;
+                    ol = l & 0x7FFFu;
+                }
+            }
+        }
+        if (!join) {
+            if (sb >= s_lo) *glb(j.cstate + col) = ol | (oc << 31);
+            return;
+        }
+        // join: [trailing run of the column of U] [middle] [leading run of row col of U]
+        uint32_t mc, ml;
+        if (j.theiler == 0) { mc = 1; ml = 1; }
+        else {
+            const int w = j.theiler;
+            const int up = col < w - 1 ? col : w - 1;
+            const int dn = (n - 1 - col) < w - 1 ? (n - 1 - col) : w - 1;
+            mc = 0;
+            ml = (uint32_t)(up + 1 + dn);
+        }
+        if (ol && oc == mc) ol += ml;
+        else { emit_line(L, j, oc, ol); oc = mc; ol = ml; }
+        if (has_row) {
+            uint32_t hc, hl;
+            if (j.segs > 1) {
+                row_pieces(L, j, col, hc, hl);
+            } else {
+                const uint32_t ld = *glb(j.lead + col);
+                hc = ld >> 31;
+                hl = ld & 0x7FFFFFFFu;
+            }
+            if (oc == hc) ol += hl;
+            else { emit_line(L, j, oc, ol); oc = hc; ol = hl; }
+        }
+        emit_line(L, j, oc, ol);
+    } else if (line < 2 * lines) {
+        // ---- diagonal k of U (and its mirror) ----
+        const int k = (int)(line - lines);
+        if (k >= wp && j.segs > 1) {
+            // its pieces in the (strip, segment) blocks it crosses, in order
+            const int r1 = n - 1 - k;
+            const int s_end = r1 / H;                           // >= s_lo
+            const int sb = s_end < s_hi - 1 ? s_end : s_hi - 1;
+            uint32_t open = carried ? (uint32_t)*glb(j.dstate + k) : 0u;
+            for (int s = s_lo; s <= sb; ++s) {
+                const int ra = s * H;
+                const int rb = r1 < s * H + H - 1 ? r1 : s * H + H - 1;
+                const int ca = ra + k, cb = rb + k;
+                const int xs = ((s * H + wp) >> 6) * 64;   // the strip's first column tile
+                for (int g = seg_of(j, ca); g <= seg_of(j, cb); ++g) {
+                    const int g0 = (j.seg_base + g * j.seg_tiles) * 64;
+                    const int lo = ca > g0 ? ca : g0;
+                    const int hi = cb < g0 + j.seg_tiles * 64 - 1 ? cb : g0 + j.seg_tiles * 64 - 1;
+                    const uint32_t len = (uint32_t)(hi - lo + 1);
+                    const bool last = rb == r1 && hi == cb;
+                    const int bx0 = g0 > xs ? g0 : xs;      // the block's first column
+                    const int64_t idx = (int64_t)((s - s_lo) * j.segs + g) * j.dw +
+                                        (s * H + H - 1 - bx0) + k;
+                    const uint32_t fb = *glb(j.dfirst + idx);
+                    if (!last && fb == len) { open += len; continue; }
+                    if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
+                    open = last ? 0u : (uint32_t)*glb(j.dlast + idx);
+                }
+            }
+            if (s_end > sb) *glb(j.dstate + k) = open;
+        } else if (k >= wp) {
+            const int s_last = (n - 1 - k) / H;                 // >= s_lo
+            const int sb = s_last < s_hi - 1 ? s_last : s_hi - 1;
+            uint32_t open = carried ? (uint32_t)*glb(j.dstate + k) : 0u;
+            for (int s0 = s_lo; s0 <= sb; s0 += kStitchBatch) {
+                uint32_t fv[kStitchBatch], lv[kStitchBatch];
+#pragma unroll
+                for (int u = 0; u < kStitchBatch; ++u) {
+                    const int s = s0 + u;
+                    if (s <= sb) {
+                        const int64_t idx = strip_offset(s, n, wp, H) - j.soff_lo + (k - wp);
+                        fv[u] = *glb(j.dfirst + idx);
+                        lv[u] = *glb(j.dlast + idx);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kStitchBatch; ++u) {
+                    const int s = s0 + u;
+                    if (s > sb) break;
+                    const uint32_t fb = fv[u];
+                    if (s < s_last && fb == (uint32_t)H) { open += H; continue; }
+                    if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
+                    open = s < s_last ? lv[u] : 0u;
+                }
+            }
+            if (s_last > sb) *glb(j.dstate + k) = open;
+        } else if (k == 0 && j.theiler == 0 && s_lo == 0) {
+            // main diagonal: every cell (i,i) is recurrent (distance 0 <= eps)
+            emit(L.bd, kCapD, j.hd, (uint32_t)n, 1u, (uint32_t)n, j.flag);
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__restrict__ jobs,
                                                            int njobs) {
     __shared__ StitchLds L;
@@ -1518,129 +1692,10 @@ __global__ void __launch_bounds__(kStitchThreads) k_stitch(const JobDesc *__rest
         if (jobs[mid].stitch_block0 <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
     }
     const JobDesc &j = jobs[lo];
-    const int n = j.n, wp = j.wp, H = j.H;
+    const int n = j.n;
     const int64_t line = (int64_t)(blockIdx.x - j.stitch_block0) * blockDim.x + threadIdx.x;
-
-    if (j.mode != kModeAuto) {
-        stitch_full(L, j, line);
-    } else if (line < n) {
-        // ---- column j of the full matrix ----
-        const int col = (int)line;
-        uint32_t oc = 0, ol = 0;   // open run after folding column `col` of U
-        if (col >= wp) {
-            const int s_last = (col - wp) / H;
-            // The summaries of kStitchBatch strips are loaded before any is
-            // folded, so a thread has that many loads in flight.
-            for (int s0 = 0; s0 <= s_last; s0 += kStitchBatch) {
-                uint32_t fv[kStitchBatch], lv[kStitchBatch];
-#pragma unroll
-                for (int u = 0; u < kStitchBatch; ++u) {
-                    const int s = s0 + u;
-                    if (s <= s_last) {
-                        const int64_t idx = strip_offset(s, n, wp, H) + (col - s * H - wp);
-                        fv[u] = *glb(j.vfirst + idx);
-                        lv[u] = *glb(j.vlast + idx);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kStitchBatch; ++u) {
-                    const int s = s0 + u;
-                    if (s > s_last) break;
-                    const uint32_t Ls = s < s_last ? (uint32_t)H : (uint32_t)(col - wp - s * H + 1);
-                    const uint32_t f = fv[u], l = lv[u];
-                    const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
-                    if (fl == Ls) {   // the segment is one run
-                        if (ol && oc == fc) ol += Ls;
-                        else { emit_line(L, j, oc, ol); oc = fc; ol = Ls; }
-                    } else {
-                        if (ol && oc == fc) emit_line(L, j, fc, ol + fl);
-                        else { emit_line(L, j, oc, ol); emit_line(L, j, fc, fl); }
-                        oc = l >> 15;
-                        ol = l & 0x7FFFu;
-                    }
-                }
-            }
-        }
-        // join: [trailing run of the column of U] [middle] [leading run of row col of U]
-        uint32_t mc, ml;
-        if (j.theiler == 0) { mc = 1; ml = 1; }
-        else {
-            const int w = j.theiler;
-            const int up = col < w - 1 ? col : w - 1;
-            const int dn = (n - 1 - col) < w - 1 ? (n - 1 - col) : w - 1;
-            mc = 0;
-            ml = (uint32_t)(up + 1 + dn);
-        }
-        if (ol && oc == mc) ol += ml;
-        else { emit_line(L, j, oc, ol); oc = mc; ol = ml; }
-        if (col + wp <= n - 1) {
-            uint32_t hc, hl;
-            if (j.segs > 1) {
-                row_pieces(L, j, col, hc, hl);
-            } else {
-                const uint32_t ld = *glb(j.lead + col);
-                hc = ld >> 31;
-                hl = ld & 0x7FFFFFFFu;
-            }
-            if (oc == hc) ol += hl;
-            else { emit_line(L, j, oc, ol); oc = hc; ol = hl; }
-        }
-        emit_line(L, j, oc, ol);
-    } else if (line < 2 * (int64_t)n) {
-        // ---- diagonal k of U (and its mirror) ----
-        const int k = (int)(line - n);
-        if (k >= wp && j.segs > 1) {
-            // its pieces in the (strip, segment) blocks it crosses, in order
-            const int r1 = n - 1 - k;
-            uint32_t open = 0;
-            for (int s = 0; s <= r1 / H; ++s) {
-                const int ra = s * H;
-                const int rb = r1 < s * H + H - 1 ? r1 : s * H + H - 1;
-                const int ca = ra + k, cb = rb + k;
-                const int xs = ((s * H + wp) >> 6) * 64;   // the strip's first column tile
-                for (int g = seg_of(j, ca); g <= seg_of(j, cb); ++g) {
-                    const int g0 = (j.seg_base + g * j.seg_tiles) * 64;
-                    const int lo = ca > g0 ? ca : g0;
-                    const int hi = cb < g0 + j.seg_tiles * 64 - 1 ? cb : g0 + j.seg_tiles * 64 - 1;
-                    const uint32_t len = (uint32_t)(hi - lo + 1);
-                    const bool last = rb == r1 && hi == cb;
-                    const int bx0 = g0 > xs ? g0 : xs;      // the block's first column
-                    const int64_t idx = (int64_t)(s * j.segs + g) * j.dw + (s * H + H - 1 - bx0) + k;
-                    const uint32_t fb = *glb(j.dfirst + idx);
-                    if (!last && fb == len) { open += len; continue; }
-                    if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
-                    open = last ? 0u : (uint32_t)*glb(j.dlast + idx);
-                }
-            }
-        } else if (k >= wp) {
-            const int s_last = (n - 1 - k) / H;
-            uint32_t open = 0;
-            for (int s0 = 0; s0 <= s_last; s0 += kStitchBatch) {
-                uint32_t fv[kStitchBatch], lv[kStitchBatch];
-#pragma unroll
-                for (int u = 0; u < kStitchBatch; ++u) {
-                    const int s = s0 + u;
-                    if (s <= s_last) {
-                        const int64_t idx = strip_offset(s, n, wp, H) + (k - wp);
-                        fv[u] = *glb(j.dfirst + idx);
-                        lv[u] = *glb(j.dlast + idx);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kStitchBatch; ++u) {
-                    const int s = s0 + u;
-                    if (s > s_last) break;
-                    const uint32_t fb = fv[u];
-                    if (s < s_last && fb == (uint32_t)H) { open += H; continue; }
-                    if (open + fb) emit_stitch(L.bd, kCapD, j.hd, open + fb, 2u, (uint32_t)n, j.flag);
-                    open = s < s_last ? lv[u] : 0u;
-                }
-            }
-        } else if (k == 0 && j.theiler == 0) {
-            // main diagonal: every cell (i,i) is recurrent (distance 0 <= eps)
-            emit(L.bd, kCapD, j.hd, (uint32_t)n, 1u, (uint32_t)n, j.flag);
-        }
-    }
+    if (j.mode != kModeAuto) stitch_full(L, j, line);
+    else stitch_auto(L, j, line);
     __syncthreads();
     const int hl = n + 1;
     for (int t = threadIdx.x; t < kCapW; t += blockDim.x) {
@@ -1877,16 +1932,18 @@ int group_key(const Job &jb) {
 
 struct Layout {
     int H, nstrips;
+    int band, nbands;      // strips per row band (auto mode) and the number of bands
     int segs, seg_tiles;   // column segments per strip and their width (tiles)
     int seg_base;          // first column tile of segment 0
-    int64_t hentries;      // row pieces (auto, segs > 1): n * segs
-    int items;             // work items: nstrips * segs
+    int64_t hentries;      // row pieces (auto, segs > 1): rows of one band * segs
+    int items;             // work items of the largest band: band * segs
     int dw;                // full matrix: diagonal summary slots per block
-    int64_t ventries;      // vertical summary entries per array (first, last)
-    int64_t dentries;      // diagonal summary entries per array
+    int64_t ventries;      // vertical summary entries per array (first, last), one band
+    int64_t dentries;      // diagonal summary entries per array, one band
     int64_t tail_len;
     int64_t box_floats;    // column boxes (header + records), 0 if none
-    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, off_hf, off_hl, off_box, bytes;
+    size_t off_tail, off_lead, off_vf, off_vl, off_df, off_dl, off_ent, off_hf, off_hl, off_box,
+        off_cs, off_ds, bytes;
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -1894,6 +1951,9 @@ size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 // Work items a full-matrix job is cut into (strips x column segments): a few
 // times the workgroups one launch keeps resident (256 CUs x 3).
 constexpr int kTargetItems = 2048;
+// Work items per row band of a banded job: every band ends with a partly
+// idle round of work items, so its items are made shorter.
+constexpr int kBandItems = 8192;
 
 // Offset of the first evaluated diagonal of U, max(theiler, 1), clamped to n:
 // every window of n or more masks the whole matrix alike, and the clamp keeps
@@ -1910,17 +1970,17 @@ int default_waves_impl(int64_t n) {
     return 4;
 }
 
-// Column segments of an auto-mode job when it runs alone: enough for about
-// kTargetItems work items, each at least 64 tiles wide; 1 for jobs whose
+// Column segments of an auto-mode job when it runs alone (`nstrips`: the
+// strips of one launch, i.e. of one row band): enough for about `target`
+// work items, each at least 64 tiles wide; 1 for jobs whose
 // first strip is shorter than 128 tiles (their chains are short) or that
 // have half that many strips already (the 1,048,576-point workload has 2,048,
 // the paper's 1,000,001-point sine 1,954: cutting it in two measured 5%
 // slower, the extra summaries costing more than the shorter chains gain).
-int auto_segs_max(int64_t n, int wp, int H) {
-    const int nstrips = n - wp > 0 ? (int)((n - wp + H - 1) / H) : 0;
+int auto_segs_max(int64_t n, int wp, int H, int nstrips, int target) {
     const int T0 = (int)((n - 1) / 64 - wp / 64 + 1);
-    if (nstrips < 1 || T0 < 128 || 2 * nstrips > kTargetItems) return 1;
-    return (int)std::max<int64_t>(1, std::min<int64_t>((kTargetItems + nstrips - 1) / nstrips, T0 / 64));
+    if (nstrips < 1 || T0 < 128 || 2 * nstrips > target) return 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((target + nstrips - 1) / nstrips, T0 / 64));
 }
 
 Layout layout_of(const Job &jb) {
@@ -1930,19 +1990,24 @@ Layout layout_of(const Job &jb) {
     L.H = 64 * (jb.waves > 0 ? jb.waves : default_waves_impl(n));
     if (jb.mode == kModeAuto) {
         L.nstrips = n - wp > 0 ? (int)((n - wp + L.H - 1) / L.H) : 0;
-        // sum over strips of (n - wp - s H) entries
-        L.ventries = (int64_t)L.nstrips * (n - wp) -
-                     (int64_t)L.H * ((int64_t)L.nstrips * (L.nstrips - 1) / 2);
+        // Row bands: the summaries hold the strips of one band (the first,
+        // whose strips are the longest); the open runs of every line pass
+        // from band to band in per-line carries.
+        L.band = jb.band_strips > 0 && jb.band_strips < L.nstrips ? jb.band_strips : L.nstrips;
+        L.nbands = L.band > 0 ? (L.nstrips + L.band - 1) / L.band : 1;
+        // sum over the band's strips of (n - wp - s H) entries
+        L.ventries = strip_offset(L.band, (int32_t)n, wp, L.H);
         // Segments: as set on the job, else the most it could be given.
         const int T0 = (int)((n - 1) / 64 - wp / 64 + 1);
-        int segs = jb.segs > 0 ? jb.segs : auto_segs_max(n, wp, L.H);
+        int segs = jb.segs > 0 ? jb.segs
+                               : auto_segs_max(n, wp, L.H, L.band, L.nbands > 1 ? kBandItems : kTargetItems);
         L.seg_base = wp / 64;
         L.seg_tiles = (T0 + segs - 1) / segs;
         L.segs = segs > 1 ? (T0 + L.seg_tiles - 1) / L.seg_tiles : 1;
         if (L.segs > 1) {
             L.dw = L.seg_tiles * 64 + L.H - 1;
-            L.dentries = (int64_t)L.nstrips * L.segs * L.dw;
-            L.hentries = n * L.segs;
+            L.dentries = (int64_t)L.band * L.segs * L.dw;
+            L.hentries = std::min<int64_t>(n, (int64_t)L.band * L.H) * L.segs;
         } else {
             L.dw = 0;
             L.dentries = L.ventries;
@@ -1968,8 +2033,10 @@ Layout layout_of(const Job &jb) {
         L.ventries = (int64_t)L.nstrips * nb;
         L.dentries = (int64_t)L.nstrips * L.segs * L.dw;
         L.hentries = 0;
+        L.band = L.nstrips;
+        L.nbands = 1;
     }
-    L.items = L.nstrips * L.segs;
+    L.items = L.band * L.segs;
     if (L.ventries < 1) L.ventries = 1;
     if (L.dentries < 1) L.dentries = 1;
     L.tail_len = jb.mode == kModeMatrix ? 0 : 64 + (int64_t)(jb.kp.m - 1) * jb.kp.tau;
@@ -1990,6 +2057,11 @@ Layout layout_of(const Job &jb) {
     L.box_floats = (jb.mode != kModeMatrix && jb.kp.m <= kMaxM)
                        ? kBoxHeader + ((ncols - 1) / 64 + 1) * (int64_t)kBoxStride : 0;
     L.off_box = off; off += a256(sizeof(float) * (size_t)L.box_floats);
+    // Per-line carries between bands: the open run of each column of U and
+    // of each diagonal.
+    const size_t carries = L.nbands > 1 ? (size_t)n : 0;
+    L.off_cs = off; off += a256(sizeof(uint32_t) * carries);
+    L.off_ds = off; off += a256(sizeof(uint32_t) * carries);
     L.bytes = off;
     return L;
 }
@@ -2040,6 +2112,13 @@ JobDesc make_desc(const Job &jb, const Layout &lay, int strip_base, int stitch_b
     d.dw = lay.dw;
     d.hfirst = lay.hentries > 0 ? reinterpret_cast<uint32_t *>(scr + lay.off_hf) : nullptr;
     d.hlast = lay.hentries > 0 ? reinterpret_cast<uint32_t *>(scr + lay.off_hl) : nullptr;
+    d.s_lo = 0;
+    d.s_hi = lay.band;
+    d.band_strips = lay.band;
+    d.nbands = lay.nbands;
+    d.soff_lo = 0;
+    d.cstate = lay.nbands > 1 ? reinterpret_cast<uint32_t *>(scr + lay.off_cs) : nullptr;
+    d.dstate = lay.nbands > 1 ? reinterpret_cast<uint32_t *>(scr + lay.off_ds) : nullptr;
     d.c_last = (int32_t)((ncols - 1) / 64);
     d.tail_len = (int32_t)lay.tail_len;
     d.strip_base = strip_base;
@@ -2081,6 +2160,36 @@ int stitch_blocks_of(const Job &jb) {
 }  // namespace
 
 size_t engine_job_scratch_bytes(const Job &job) { return layout_of(job).bytes; }
+
+int engine_band_strips(const Job &job, size_t limit) {
+    if (job.mode != kModeAuto || limit == 0) return 0;
+    Job jb = job;
+    jb.band_strips = 0;
+    const Layout all = layout_of(jb);
+    if (all.bytes <= limit || all.nstrips <= 1) return 0;
+    // The largest band whose scratch fits (the scratch grows with the band,
+    // up to the jumps where the column segments per strip change).
+    int lo = 1, hi = all.nstrips - 1;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        jb.band_strips = mid;
+        if (layout_of(jb).bytes <= limit) lo = mid; else hi = mid - 1;
+    }
+    jb.band_strips = lo;
+    while (lo > 1 && layout_of(jb).bytes > limit) jb.band_strips = --lo;
+    return lo;
+}
+
+JobPlan engine_job_plan(const Job &job) {
+    const Layout lay = layout_of(job);
+    JobPlan p{};
+    p.bands = lay.nbands;
+    p.band_strips = lay.band;
+    p.segs = lay.segs;
+    p.strip_rows = lay.H;
+    p.scratch_bytes = lay.bytes;
+    return p;
+}
 
 int engine_default_waves(int64_t n) { return default_waves_impl(n); }
 
@@ -2196,6 +2305,38 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
     hipLaunchKernelGGL(k_box_probe, dim3(njobs), dim3(kProbeThreads), 0, st, ddesc);
 
     if (phases) hipEventRecord(phases->ev[1], st);
+    if (njobs == 1 && hdesc[0].nbands > 1) {
+        // One job in row bands: per band the tile kernel over the band's
+        // strips, then the stitch of the lines those strips cross.
+        const JobDesc &d = hdesc[0];
+        const Job &jb = jobs_in[0];
+        TileKernel kern = tile_kernel(jb.mode, jb.kp.norm, jb.kp.m);
+        int occ = 0;
+        const size_t lds = strip_lds_bytes(jb.waves);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * jb.waves, lds) != hipSuccess ||
+            occ < 1)
+            occ = 1;
+        const int full_grid = groups_req > 0 ? groups_req : ncu * occ;
+        for (int b = 0; b < d.nbands; ++b) {
+            const int lo = b * d.band_strips;
+            const int hi = std::min(lo + d.band_strips, d.nstrips);
+            const int items = (hi - lo) * d.segs;
+            const int64_t lines = 2 * ((int64_t)d.n - (int64_t)lo * d.H);
+            hipLaunchKernelGGL(k_band, dim3(1), dim3(64), 0, st, ddesc, dgroups, dcounters, b);
+            if (items > 0)
+                hipLaunchKernelGGL(kern, dim3(std::min(full_grid, items)), dim3(64 * jb.waves), lds, st,
+                                   ddesc, dgroups, 0, dcounters);
+            if (phases && b == d.nbands - 1) hipEventRecord(phases->ev[2], st);
+            if (lines > 0)
+                hipLaunchKernelGGL(k_stitch, dim3((unsigned)((lines + kStitchThreads - 1) / kStitchThreads)),
+                                   dim3(kStitchThreads), 0, st, ddesc, 1);
+        }
+        hipLaunchKernelGGL(k_stats_moments, dim3(stat_grid, 1), dim3(kStatThreads), 0, st, ddesc);
+        hipLaunchKernelGGL(k_stats_entropy, dim3(stat_grid, 1), dim3(kStatThreads), 0, st, ddesc);
+        hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(256), 0, st, ddesc, 1);
+        if (phases) hipEventRecord(phases->ev[3], st);
+        return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
+    }
     int active = 0;
     for (int g = 0; g < ngroups; ++g) active += hgroups[g].items > 0;
     const bool fork = aux && aux->count > 0 && active > 1;

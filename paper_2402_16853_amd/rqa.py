@@ -177,6 +177,22 @@ class RQA:
     def set_tiling(self, waves_per_group: int = 0, groups: int = 0):
         check(lib().rqa_set_tiling(self._h, int(waves_per_group), int(groups)), "rqa_set_tiling")
 
+    def set_workspace_limit(self, nbytes: int = 0):
+        """Bound the line summaries of a one-series run to `nbytes` of device
+        memory (0: a quarter of the device's memory); a run that would need more
+        walks its strips in row bands with the same results."""
+        check(lib().rqa_set_workspace_limit(self._h, int(nbytes)), "rqa_set_workspace_limit")
+
+    def last_plan(self) -> dict:
+        """How the last run was cut: row bands, strips per band, column
+        segments per strip, rows per strip, workspace bytes of its first job."""
+        b, k, g, r = (ctypes.c_int32() for _ in range(4))
+        w = ctypes.c_int64()
+        check(lib().rqa_last_plan(self._h, ctypes.byref(b), ctypes.byref(k), ctypes.byref(g),
+                                  ctypes.byref(r), ctypes.byref(w)), "rqa_last_plan")
+        return {"bands": b.value, "band_strips": k.value, "segs": g.value, "strip_rows": r.value,
+                "workspace_bytes": w.value}
+
     def run(self, series, stream=None):
         """Enqueue the RQA of a device series (asynchronous)."""
         s = _device_series(series)

@@ -76,6 +76,13 @@ def test_handle_lifecycle_and_host_errors():
     assert L.rqa_result_batch_all(None, ctypes.cast(many, ctypes.c_void_p), None, 4) == -1
     assert L.rqa_set_tiling(h, 9, 0) == -1
     assert L.rqa_set_tiling(h, 4, 0) == 0
+    assert L.rqa_set_workspace_limit(h, -1) == -1
+    assert L.rqa_set_workspace_limit(None, 1 << 30) == -1
+    assert L.rqa_set_workspace_limit(h, 1 << 30) == 0
+    assert L.rqa_set_workspace_limit(h, 0) == 0
+    b = ctypes.c_int32()
+    assert L.rqa_last_plan(h, ctypes.byref(b), None, None, None, None) == -7   # no run yet
+    assert L.rqa_last_plan(None, ctypes.byref(b), None, None, None, None) == -1
     L.rqa_destroy(h)
     L.rqa_destroy(None)
 
