@@ -246,6 +246,15 @@ int rqa_set_workspace_limit(rqa_handle *h, int64_t bytes);
 int rqa_last_plan(const rqa_handle *h, int32_t *bands, int32_t *band_strips, int32_t *segs,
                   int32_t *strip_rows, int64_t *workspace_bytes);
 
+/* The same cut computed on the host, without a device or a run: for a series
+ * of n_points run alone with `waves` waves per workgroup (1..8; 0 = the
+ * library's default shape) and line summaries bounded by limit_bytes (0 = no
+ * bound, one band).  Any output pointer may be NULL.  RQA_EINVAL for invalid
+ * parameters or arguments, RQA_ETOOSHORT if the series has no delay vector. */
+int rqa_workspace_plan(const rqa_params *p, int64_t n_points, int32_t waves, int64_t limit_bytes,
+                       int32_t *bands, int32_t *band_strips, int32_t *segs,
+                       int64_t *workspace_bytes);
+
 /* For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
  * RQA as rqa_run + rqa_result of one device series under the parameters *p,

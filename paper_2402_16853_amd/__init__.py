@@ -5,5 +5,6 @@ diagonal / vertical / white-vertical line histograms) runs in hand-written HIP
 kernels for gfx950 behind the C ABI of ``librqa.so`` (``include/rqa.h``); this
 package only marshals arguments to it.
 """
-from .rqa import RQA, RQAResult, RQAError, Server, measures_from_hist, make_params, norm_code  # noqa: F401
+from .rqa import (RQA, RQAResult, RQAError, Server, measures_from_hist, make_params,  # noqa: F401
+                  norm_code, workspace_plan)
 from ._lib import LIB_PATH, SIGNATURES  # noqa: F401

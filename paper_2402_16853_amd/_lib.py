@@ -77,6 +77,9 @@ SIGNATURES = {
     "rqa_server_destroy": (None, [_P]),
     "rqa_run_static": (ctypes.c_int, [ctypes.POINTER(RqaParams), _P, _I64, _P, _I64, _P, _P]),
     "rqa_set_workspace_limit": (ctypes.c_int, [_P, _I64]),
+    "rqa_workspace_plan": (ctypes.c_int, [ctypes.POINTER(RqaParams), _I64, _I32, _I64,
+                                          ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                          ctypes.POINTER(_I32), ctypes.POINTER(_I64)]),
     "rqa_last_plan": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_I64)]),

@@ -740,6 +740,30 @@ int rqa_last_launch(const rqa_handle *h, int32_t *waves, int32_t *graph_replay) 
     return RQA_OK;
 }
 
+int rqa_workspace_plan(const rqa_params *p, int64_t n_points, int32_t waves, int64_t limit_bytes,
+                       int32_t *bands, int32_t *band_strips, int32_t *segs,
+                       int64_t *workspace_bytes) {
+    if (!p || waves < 0 || waves > 8 || limit_bytes < 0) return RQA_EINVAL;
+    int rc = validate_params(*p);
+    if (rc != RQA_OK) return rc;
+    const int64_t nv = n_points - static_cast<int64_t>(p->m - 1) * p->tau;
+    if (nv < 1) return RQA_ETOOSHORT;
+    if (nv > (int64_t(1) << 31) - 2) return RQA_EINVAL;
+    Job jb;
+    jb.n_points = n_points;
+    jb.n_vec = nv;
+    jb.n_cols = nv;
+    jb.kp = make_kparams(*p);
+    jb.waves = waves > 0 ? waves : engine_default_waves(nv);
+    jb.band_strips = engine_band_strips(jb, static_cast<size_t>(limit_bytes));
+    const JobPlan plan = engine_job_plan(jb);
+    if (bands) *bands = plan.bands;
+    if (band_strips) *band_strips = plan.band_strips;
+    if (segs) *segs = plan.segs;
+    if (workspace_bytes) *workspace_bytes = static_cast<int64_t>(plan.scratch_bytes);
+    return RQA_OK;
+}
+
 int rqa_set_workspace_limit(rqa_handle *h, int64_t bytes) {
     if (!h || bytes < 0) return RQA_EINVAL;
     h->ws_limit = bytes;

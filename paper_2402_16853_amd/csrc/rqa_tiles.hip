@@ -921,7 +921,8 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     bool sync_ok = true;
     // Given matrix: the next tile's row word is loaded while the current tile
     // is processed (one load in flight per lane hides the memory latency that
-    // otherwise sets the pace of a strip).
+    // otherwise sets the pace of a strip; loading 2, 4 or 8 tiles ahead
+    // measured no faster).
     const auto mrow = MODE == kModeMatrix && i < n ? glb(j.bits) + (int64_t)i * j.words : nullptr;
     uint64_t mnext = 0;
     if constexpr (MODE == kModeMatrix) {
@@ -1948,12 +1949,16 @@ struct Layout {
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
-// Work items a full-matrix job is cut into (strips x column segments): a few
-// times the workgroups one launch keeps resident (256 CUs x 3).
+// Work items (strips x column segments) a single series run alone is cut
+// into: a few times the workgroups one launch keeps resident (256 CUs x 3).
 constexpr int kTargetItems = 2048;
-// Work items per row band of a banded job: every band ends with a partly
-// idle round of work items, so its items are made shorter.
+// Work items per row band of a banded job, and of a full-matrix job: their
+// items are shorter chains of tiles, so that the launch's last, partly idle
+// round of items is short (cross recurrence of 2 x 262,144 points 10.3 ->
+// 9.3 ms, given 65,516^2 matrix 0.72 -> 0.50 ms against 2,048 items;
+// 16,384 items made the given matrix slower again).
 constexpr int kBandItems = 8192;
+constexpr int kFullItems = 8192;
 
 // Offset of the first evaluated diagonal of U, max(theiler, 1), clamped to n:
 // every window of n or more masks the whole matrix alike, and the clamp keeps
@@ -2016,14 +2021,14 @@ Layout layout_of(const Job &jb) {
     } else {
         // A strip of a full matrix walks every column tile; its chain of
         // tiles is cut into column segments walked by different workgroups,
-        // enough of them for about kTargetItems work items, each at least
+        // enough of them for about kFullItems work items, each at least
         // max(8, H/64) tiles wide (so a diagonal crosses at most one segment
         // edge inside a strip).
         const int64_t nb = jb.n_cols;
         L.nstrips = (int)((n + L.H - 1) / L.H);
         const int T = (int)((nb - 1) / 64 + 1);
         const int min_tiles = std::max(8, L.H / 64);
-        int segs = (int)std::min<int64_t>((kTargetItems + L.nstrips - 1) / L.nstrips,
+        int segs = (int)std::min<int64_t>((kFullItems + L.nstrips - 1) / L.nstrips,
                                           std::max(1, T / min_tiles));
         segs = std::max(segs, 1);
         L.seg_base = 0;

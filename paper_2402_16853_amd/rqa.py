@@ -343,6 +343,22 @@ def measures_from_hist(diag, vert, white, params) -> dict:
     return _measures_dict(ms)
 
 
+def workspace_plan(params, n_points: int, waves: int = 0, limit_bytes: int = 0) -> dict:
+    """How a run of one series of n_points would be cut (host only): row bands,
+    strips per band, column segments per strip and the line-summary workspace,
+    for `waves` waves per workgroup (0: default) and a bound of limit_bytes
+    (0: none)."""
+    p = params if isinstance(params, RqaParams) else make_params(
+        params.m, params.tau, params.eps, params.norm, params.lmin, params.vmin, params.wmin,
+        params.theiler)
+    b, k, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    w = ctypes.c_int64()
+    check(lib().rqa_workspace_plan(ctypes.byref(p), int(n_points), int(waves), int(limit_bytes),
+                                   ctypes.byref(b), ctypes.byref(k), ctypes.byref(g),
+                                   ctypes.byref(w)), "rqa_workspace_plan")
+    return {"bands": b.value, "band_strips": k.value, "segs": g.value, "workspace_bytes": w.value}
+
+
 class Server:
     """Continuous-batching RQA server over librqa's serving API."""
 

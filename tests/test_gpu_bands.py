@@ -203,3 +203,66 @@ def test_four_million_points(cuda):
     assert lv + lw == n * n, (lv, lw, n)
     # the recurrence rate stays that of the 1M-point series (same attractor, same eps rule)
     assert 0.0005 < a.measures["rr"] < 0.005, a.measures["rr"]
+
+
+def test_tiny_series_and_wide_windows(cuda, oracle_lib):
+    """Short series (a strip or two), windows at and beyond n: one strip per
+    band, against the oracle."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    rng = np.random.default_rng(44)
+    for n in (3, 64, 65, 130, 300):
+        s = rng.random(n).astype(np.float32)
+        for w in (0, 1, 2, 63, 64, n - 1, n, n + 5):
+            p = Params(m=1, tau=1, eps=0.3, norm=3, theiler=w)
+            ref = oracle_lib.rqa(s, p)
+            comp = RQA.from_params(p)
+            comp.set_tiling(1, 0)
+            _announce("tiny", n=n, w=w)
+            res, plan = run(comp, torch.from_numpy(s).to(cuda), 1)
+            comp.close()
+            assert_same(res, *ref, tag=f"tiny n={n} w={w} plan {plan}")
+
+
+def test_batch_of_one_window_in_bands(cuda, oracle_lib):
+    """rqa_run_batch with a single window is a run alone: it may be banded."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    s, p = workload("lorenz", seed=9, n=9_000)
+    ds = torch.from_numpy(s).to(cuda)
+    ref = oracle_lib.rqa(s[500:7_500], p)
+    comp = RQA.from_params(p)
+    comp.set_tiling(2, 0)
+    comp.set_workspace_limit(1)
+    _announce("batch of one", n=7_000)
+    comp.run_batch(ds, [500], [7_000])
+    res = comp.result_batch(0)
+    plan = comp.last_plan()
+    comp.close()
+    assert plan["bands"] > 1, plan
+    assert_same(res, *ref, tag=f"batch of one {plan}")
+
+
+def test_banded_graph_replays(cuda, oracle_lib):
+    """Identical repeated banded launches are captured once into a hipGraph
+    and replayed; the band kernel rewrites the descriptors inside the graph.
+    Every replay, with the program's own work in between, equals the oracle."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    s, p = workload("lorenz", seed=4, n=6_000)
+    ref = oracle_lib.rqa(s, p)
+    ds = torch.from_numpy(s).to(cuda)
+    comp = RQA.from_params(p)
+    comp.set_tiling(1, 0)
+    comp.set_workspace_limit(1)
+    replays = 0
+    for k in range(5):
+        _announce("banded replay", k=k)
+        res = comp(ds)
+        replays += comp.last_launch()["graph_replay"]
+        assert comp.last_plan()["bands"] > 1
+        assert_same(res, *ref, tag=f"run {k}")
+        torch.cuda.synchronize()
+        (ds * 2.0).sum().item()            # unrelated eager work between replays
+    comp.close()
+    assert replays >= 3, replays
