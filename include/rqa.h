@@ -202,10 +202,11 @@ int rqa_measures_from_hist(const uint64_t *diag, const uint64_t *vert,
                            rqa_measures *out);
 
 /* Tile-shape override: waves per workgroup (1..8, rows per strip = 64*waves;
- * 0 = chosen by the built-in autotuner, which times the candidate shapes on the
- * first runs of each launch signature; RQA_AUTOTUNE_CACHE=<file> persists its
- * choices) and workgroups per launch (0 = fill the device).  Results never
- * depend on these. */
+ * 0 = chosen by the built-in autotuner, which times the candidate shapes 2, 4
+ * and 8 waves on the first runs of each launch signature, the default shape
+ * first; a shape more than 10% slower than the best so far ends the trials
+ * beyond it; RQA_AUTOTUNE_CACHE=<file> persists its choices) and workgroups
+ * per launch (0 = fill the device).  Results never depend on these. */
 int rqa_set_tiling(rqa_handle *h, int32_t waves_per_group, int32_t groups);
 
 /* Phase timing (hipEvents recorded on the run's stream).  With profiling on,
