@@ -570,6 +570,38 @@ def bench_served(args, torch, RQA, Server, reqs):
         c.result(histograms=False)
         t_seq += time.perf_counter() - t0
         c.close()
+    # the stream's largest job alone: through the server (nothing else queued)
+    # and through rqa_run on a handle of its own, warm, median of 5
+    big = max(range(len(reqs)), key=lambda k: float(nvec[k]) * nvec[k])
+    srv = Server(budget, streams=4)
+    srv.wait(srv.submit(reqs[big].params, dser[big]), histograms=False)
+    t_srv = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        srv.wait(srv.submit(reqs[big].params, dser[big]), histograms=False)
+        t_srv.append(time.perf_counter() - t0)
+    srv.close()
+    c = RQA.from_params(reqs[big].params)
+    c.set_tiling(default_waves(nvec[big]), 0)
+    c.run(dser[big])
+    c.result(histograms=False)
+    t_run = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.run(dser[big])
+        c.result(histograms=False)
+        t_run.append(time.perf_counter() - t0)
+    plan = c.last_plan()
+    c.close()
+    largest = {"n_points": len(reqs[big].series), "n_vec": int(nvec[big]),
+               "m": reqs[big].params.m, "norm": reqs[big].params.norm,
+               "served_alone_ms": round(float(np.median(t_srv)) * 1e3, 3),
+               "run_alone_ms": round(float(np.median(t_run)) * 1e3, 3),
+               "column_segments": plan["segs"]}
+    log(f"[bench] served: largest job ({largest['n_points']} points) alone "
+        f"{largest['served_alone_ms']:.2f} ms through the server, "
+        f"{largest['run_alone_ms']:.2f} ms through rqa_run")
     lat_ms = np.array(lat) * 1e3
     return {"requests": len(reqs), "rate_hz": 200.0, "arrival_span_s": round(reqs[-1].arrival, 3),
             "cells": cells, "latency_samples": int(len(lat_ms)),
@@ -581,7 +613,8 @@ def bench_served(args, torch, RQA, Server, reqs):
                          "gcells_per_s": round(cap_cells / t_cap / 1e9, 3),
                          "sequential_s": round(t_seq, 3),
                          "sequential_gcells_per_s": round(cap_cells / t_seq / 1e9, 3),
-                         "speedup_vs_sequential": round(t_seq / t_cap, 3)}}
+                         "speedup_vs_sequential": round(t_seq / t_cap, 3)},
+            "largest_job": largest}
 
 
 def probe_valu():

@@ -1952,12 +1952,12 @@ size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 // Work items (strips x column segments) a single series run alone is cut
 // into: a few times the workgroups one launch keeps resident (256 CUs x 3).
 constexpr int kTargetItems = 2048;
-// Work items per row band of a banded job, and of a full-matrix job: their
-// items are shorter chains of tiles, so that the launch's last, partly idle
-// round of items is short (cross recurrence of 2 x 262,144 points 10.3 ->
-// 9.3 ms, given 65,516^2 matrix 0.72 -> 0.50 ms against 2,048 items;
-// 16,384 items made the given matrix slower again).
-constexpr int kBandItems = 8192;
+// Work items of a series cut into column segments (per row band when banded)
+// and of a full-matrix job: shorter chains of tiles, so that the launch's
+// last, partly idle round of items is short (cross recurrence of 2 x 262,144
+// points 10.3 -> 9.3 ms, given 65,516^2 matrix 0.72 -> 0.50 ms against 2,048
+// items; 16,384 items made the given matrix slower again).
+constexpr int kSegItems = 8192;    // (one series alone, one band or several)
 constexpr int kFullItems = 8192;
 
 // Offset of the first evaluated diagonal of U, max(theiler, 1), clamped to n:
@@ -1976,16 +1976,20 @@ int default_waves_impl(int64_t n) {
 }
 
 // Column segments of an auto-mode job when it runs alone (`nstrips`: the
-// strips of one launch, i.e. of one row band): enough for about `target`
-// work items, each at least 64 tiles wide; 1 for jobs whose
-// first strip is shorter than 128 tiles (their chains are short) or that
-// have half that many strips already (the 1,048,576-point workload has 2,048,
+// strips of one launch, i.e. of one row band): enough for about kSegItems
+// work items, each at least 64 tiles wide; 1 for jobs whose first strip is
+// shorter than 128 tiles (their chains are short) or that have more than
+// kTargetItems / 2 strips already (the 1,048,576-point workload has 2,048,
 // the paper's 1,000,001-point sine 1,954: cutting it in two measured 5%
 // slower, the extra summaries costing more than the shorter chains gain).
-int auto_segs_max(int64_t n, int wp, int H, int nstrips, int target) {
+// kSegItems rather than kTargetItems items: shorter chains measured faster
+// on dense jobs (a 199,873-vector served job at RR 5%: 13.9 ms with 2,048
+// items, 12.1 with 4,096, 11.5 with 8,192; a 300,000-point Lorenz series
+// 9.2 / 8.3 / 7.8 ms).
+int auto_segs_max(int64_t n, int wp, int H, int nstrips) {
     const int T0 = (int)((n - 1) / 64 - wp / 64 + 1);
-    if (nstrips < 1 || T0 < 128 || 2 * nstrips > target) return 1;
-    return (int)std::max<int64_t>(1, std::min<int64_t>((target + nstrips - 1) / nstrips, T0 / 64));
+    if (nstrips < 1 || T0 < 128 || 2 * nstrips > kTargetItems) return 1;
+    return (int)std::max<int64_t>(1, std::min<int64_t>((kSegItems + nstrips - 1) / nstrips, T0 / 64));
 }
 
 Layout layout_of(const Job &jb) {
@@ -2004,8 +2008,7 @@ Layout layout_of(const Job &jb) {
         L.ventries = strip_offset(L.band, (int32_t)n, wp, L.H);
         // Segments: as set on the job, else the most it could be given.
         const int T0 = (int)((n - 1) / 64 - wp / 64 + 1);
-        int segs = jb.segs > 0 ? jb.segs
-                               : auto_segs_max(n, wp, L.H, L.band, L.nbands > 1 ? kBandItems : kTargetItems);
+        int segs = jb.segs > 0 ? jb.segs : auto_segs_max(n, wp, L.H, L.band);
         L.seg_base = wp / 64;
         L.seg_tiles = (T0 + segs - 1) / segs;
         L.segs = segs > 1 ? (T0 + L.seg_tiles - 1) / L.seg_tiles : 1;
