@@ -1053,8 +1053,8 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                     }
                     if (wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
-                        *glb(j.vlast + sidx) = pk;
-                        if (st.first) *glb(j.vfirst + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;   // one run: its last is its first
+                        else *glb(j.vlast + sidx) = pk;
                     } else {
                         L.vs(slot, wave, lane) = pack_run(st);
                     }
@@ -1088,8 +1088,14 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                         L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (!FULL || dok(klo)) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        *glb(j.dlast + dbase + klo) = b;
-                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
+                        // A black run over the whole piece: the stitch reads only its first
+                        // (a white one reads as 0 and needs its last too).
+                        if (lw.first && lw.color) {
+                            *glb(j.dfirst + dbase + klo) = b;
+                        } else {
+                            *glb(j.dlast + dbase + klo) = b;
+                            if (lw.first) *glb(j.dfirst + dbase + klo) = b;
+                        }
                     }
                     left = up;
                 }
@@ -1122,8 +1128,8 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                     }
                     if (wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
-                        *glb(j.vlast + sidx) = pk;
-                        if (st.first) *glb(j.vfirst + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;   // one run: its last is its first
+                        else *glb(j.vlast + sidx) = pk;
                     } else {
                         L.vs(slot, wave, lane) = pack_run(st);
                     }
@@ -1166,8 +1172,14 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                         L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (!FULL || dok(klo)) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        *glb(j.dlast + dbase + klo) = b;
-                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
+                        // A black run over the whole piece: the stitch reads only its first
+                        // (a white one reads as 0 and needs its last too).
+                        if (lw.first && lw.color) {
+                            *glb(j.dfirst + dbase + klo) = b;
+                        } else {
+                            *glb(j.dlast + dbase + klo) = b;
+                            if (lw.first) *glb(j.dfirst + dbase + klo) = b;
+                        }
                     }
                     left = up;
                 }
@@ -1208,8 +1220,8 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                     run_segment<kVert>(Y, vwin, 0u, vhi, st, lc);
                     if (e <= 63 || wave == nw - 1) {
                         const uint16_t pk = (uint16_t)(st.len | (st.color << 15));
-                        *glb(j.vlast + sidx) = pk;
-                        if (st.first) *glb(j.vfirst + sidx) = pk;
+                        if (st.first) *glb(j.vfirst + sidx) = pk;   // one run: its last is its first
+                        else *glb(j.vlast + sidx) = pk;
                     } else {
                         L.vs(slot, wave, lane) = pack_run(st);
                     }
@@ -1268,8 +1280,14 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                         L.ds(slot, wave, lane) = pack_run(lw);
                     } else if (ok) {
                         const uint16_t b = (uint16_t)(lw.color ? lw.len : 0u);
-                        *glb(j.dlast + dbase + klo) = b;
-                        if (lw.first) *glb(j.dfirst + dbase + klo) = b;
+                        // A black run over the whole piece: the stitch reads only its first
+                        // (a white one reads as 0 and needs its last too).
+                        if (lw.first && lw.color) {
+                            *glb(j.dfirst + dbase + klo) = b;
+                        } else {
+                            *glb(j.dlast + dbase + klo) = b;
+                            if (lw.first) *glb(j.dfirst + dbase + klo) = b;
+                        }
                     }
                 }
                 left = up;
@@ -1289,8 +1307,8 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                     finish_run<kHoriz>(hctx, hs.color, hs.len, hs.first);
                 } else {
                     const uint32_t h = hs.len | (hs.color << 31);
-                    *glb(j.hlast + hctx.sum_idx) = h;
                     if (hs.first) *glb(j.hfirst + hctx.sum_idx) = h;
+                    else *glb(j.hlast + hctx.sum_idx) = h;
                 }
             }
         }
@@ -1304,8 +1322,14 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
             if (left.color || left.first) finish_run<kDiag, kDW>(lc, left.color, left.len, left.first);
         } else if (dok(kup)) {
             const uint16_t b = (uint16_t)(left.color ? left.len : 0u);
-            *glb(j.dlast + dbase + kup) = b;
-            if (left.first) *glb(j.dfirst + dbase + kup) = b;
+            // A black run over the whole piece: the stitch reads only its first
+            // (a white one reads as 0 and needs its last too).
+            if (left.first && left.color) {
+                *glb(j.dfirst + dbase + kup) = b;
+            } else {
+                *glb(j.dlast + dbase + kup) = b;
+                if (left.first) *glb(j.dfirst + dbase + kup) = b;
+            }
         }
     }
 }
