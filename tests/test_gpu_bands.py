@@ -67,6 +67,8 @@ SMALL = [
     ("sine", 4000, 2, 2, 2, 1.0, 1, 1),     # long runs across every band edge
     ("sine", 4000, 2, 2, 2, 1.0, 0, 4),
     ("logistic", 1500, 5, 1, 1, 0.4, 2, 2),
+    ("ar1", 1800, 7, 1, 2, 1.2, 1, 1),      # m beyond the register-held dimensions
+    ("ar1", 1800, 8, 2, 3, 0.6, 5, 2),
 ]
 
 
@@ -266,3 +268,27 @@ def test_banded_graph_replays(cuda, oracle_lib):
         (ds * 2.0).sum().item()            # unrelated eager work between replays
     comp.close()
     assert replays >= 3, replays
+
+
+def test_non_finite_input_in_bands(cuda):
+    """A non-finite value anywhere in the series fails the banded run with
+    RQA_ENONFINITE, as it fails the run in one band; the next finite run on
+    the same handle is exact again."""
+    import torch
+    from paper_2402_16853_amd import RQA, RQAError
+    s, p = workload("lorenz", seed=6, n=5_000)
+    bad = s.copy()
+    bad[3_333] = np.nan
+    comp = RQA.from_params(p)
+    comp.set_tiling(1, 0)
+    comp.set_workspace_limit(1)
+    good_ref = comp(torch.from_numpy(s).to(cuda))
+    _announce("non-finite in bands")
+    with pytest.raises(RQAError) as err:
+        comp(torch.from_numpy(bad).to(cuda))
+    assert "NONFINITE" in str(err.value)
+    again = comp(torch.from_numpy(s).to(cuda))
+    assert comp.last_plan()["bands"] > 1
+    for h in ("diag", "vert", "white"):
+        assert np.array_equal(getattr(again, h), getattr(good_ref, h)), h
+    comp.close()
