@@ -226,18 +226,19 @@ int rqa_last_launch(const rqa_handle *h, int32_t *waves, int32_t *graph_replay);
 
 /* Memory bound of the recombination (Sect. 4.1, Divide & Recombine: the matrix
  * is processed in parts that fit the memory, and lines crossing their borders
- * pass on through carry-over state).  A run of one series keeps, per strip of
- * rows and line, the runs at the strip's edges until they are joined; for long
- * series that is O(n^2 / strip height) bytes.  When that would exceed `bytes`,
- * the run walks the strips in row bands: each band's tile kernel writes its
- * edge runs, the band's stitch joins them into one open run per column and per
- * diagonal (O(n) carries), and the next band reuses the space.  Results are
+ * pass on through carry-over state).  A run keeps, per strip of rows and line,
+ * the runs at the strip's edges until they are joined: O(n_rows n_cols / strip
+ * height) bytes.  When that would exceed `bytes`, the run walks the strips in
+ * row bands: each band's tile kernel writes its edge runs, the band's stitch
+ * joins them into one open run per column and per diagonal (carries of
+ * O(n_rows + n_cols)), and the next band reuses the space.  Results are
  * identical (with several bands, the tile phase of rqa_get_timings also holds
  * the stitch of every band but the last).  bytes = 0 restores the default: a
- * quarter of the device's memory.  Applies to rqa_run (one series, or a batch of one window); batches
- * of several windows, cross recurrence and given matrices are not banded.
- * RQA_EINVAL for bytes < 0; a bound below what one band needs runs with one
- * strip per band (and may then fail with RQA_ENOMEM). */
+ * quarter of the device's memory.  Applies to a job run alone: rqa_run (one
+ * series, or a batch of one window), rqa_run_cross and rqa_run_matrix; batches
+ * of several windows are not banded.  RQA_EINVAL for bytes < 0; a bound below
+ * what one band needs runs with one strip per band (and may then fail with
+ * RQA_ENOMEM). */
 int rqa_set_workspace_limit(rqa_handle *h, int64_t bytes);
 
 /* How the last run was cut: row bands and strips per band (1 and all strips

@@ -277,9 +277,9 @@ int launch(rqa_handle *h, std::vector<Job> &jobs, int waves, bool trial, const s
     total += align256(kInfoBytes * static_cast<size_t>(count));
     const size_t hist_block_off = total;
     for (int32_t w = 0; w < count; ++w) jobs[w].waves = waves;
-    // A series run alone is cut into row bands when its line summaries would
-    // exceed the workspace limit.
-    if (count == 1 && jobs[0].mode == kModeAuto) {
+    // A job run alone (a series, a cross pair or a given matrix) is cut into
+    // row bands when its line summaries would exceed the workspace limit.
+    if (count == 1) {
         size_t limit = static_cast<size_t>(h->ws_limit);
         if (limit == 0) {
             int dev = 0;

@@ -853,7 +853,7 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     const int G = j.segs;
     const bool BLK = FULL || G > 1;              // per-block diagonal summaries
     const int lstrip = item / G;                 // strip within the row band (auto)
-    const int strip = (FULL ? 0 : j.s_lo) + lstrip;
+    const int strip = j.s_lo + lstrip;
     const int seg = item - lstrip * G;
     const int R0 = strip * H;
     const int R = R0 + 64 * wave;
@@ -880,7 +880,7 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     // k = x0-(R0+H-1) .. x1-1-R0 that have a cell in the block's columns [x0, x1).
     const int x0 = (c0 + ta) * 64;
     const int x1 = (c0 + tb) * 64 < nb ? (c0 + tb) * 64 : nb;
-    const int64_t vbase = FULL ? (int64_t)strip * nb : soff - R0 - wp;
+    const int64_t vbase = FULL ? (int64_t)lstrip * nb : soff - R0 - wp;
     const int64_t dbase = BLK ? (int64_t)item * j.dw + (R0 + H - 1) - x0 : soff - wp;
     const int kmin = BLK ? (FULL || x0 - (R0 + H - 1) > wp ? x0 - (R0 + H - 1) : wp) : wp;
     const int kmax = BLK ? x1 - 1 - R0 : n - 1 - R0;
@@ -914,7 +914,7 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
     // Horizontal runs: with segments, each row's piece in this block records
     // its first and last runs (hfirst / hlast); otherwise the row's first run
     // is its lead.
-    const LineCtx hctx{&j, bins, (int64_t)(i - (FULL ? 0 : j.s_lo) * H) * G + seg, G > 1, (uint32_t)i};
+    const LineCtx hctx{&j, bins, (int64_t)(i - j.s_lo * H) * G + seg, G > 1, (uint32_t)i};
     Run hs{0, 0, 0};          // horizontal run of this lane's row (auto)
     bool hstarted = false;
     Run left{0, 0, 0};        // diagonal carry from the previous tile (upper part end)
@@ -1495,15 +1495,25 @@ __device__ void row_pieces(StitchLds &L, const JobDesc &j, int r, uint32_t &lc, 
 // starts inside a strip (at the left border) has no top-edge summary there.
 __device__ __forceinline__ void stitch_full(StitchLds &L, const JobDesc &j, int64_t line) {
     const int n = j.n, nb = j.nb, H = j.H, S = j.nstrips;
+    // Strips [s_lo, s_hi) of one row band (all strips with one band): a line
+    // goes on from the open run an earlier band left in cstate / dstate, and
+    // leaves its own there unless its last piece is in this band.
+    const int s_lo = j.s_lo, s_hi = j.s_hi;
+    const bool first_band = s_lo == 0, last_band = s_hi >= S;
     if (line < nb) {
         const int col = (int)line;
         uint32_t oc = 0, ol = 0;
-        for (int s0 = 0; s0 < S; s0 += kStitchBatch) {
+        if (!first_band) {
+            const uint32_t c = *glb(j.cstate + col);
+            oc = c >> 31;
+            ol = c & 0x7FFFFFFFu;
+        }
+        for (int s0 = s_lo; s0 < s_hi; s0 += kStitchBatch) {
             uint32_t fv[kStitchBatch], lv[kStitchBatch];
 #pragma unroll
             for (int u = 0; u < kStitchBatch; ++u) {
-                const int64_t idx = (int64_t)(s0 + u) * nb + col;
-                if (s0 + u < S) {
+                const int64_t idx = (int64_t)(s0 + u - s_lo) * nb + col;
+                if (s0 + u < s_hi) {
                     fv[u] = *glb(j.vfirst + idx);
                     lv[u] = *glb(j.vlast + idx);
                 }
@@ -1511,7 +1521,7 @@ __device__ __forceinline__ void stitch_full(StitchLds &L, const JobDesc &j, int6
 #pragma unroll
             for (int u = 0; u < kStitchBatch; ++u) {
                 const int s = s0 + u;
-                if (s >= S) break;
+                if (s >= s_hi) break;
                 const uint32_t Ls = s < S - 1 ? (uint32_t)H : (uint32_t)(n - s * H);
                 const uint32_t f = fv[u], l = lv[u];
                 const uint32_t fc = f >> 15, fl = f & 0x7FFFu;
@@ -1526,16 +1536,21 @@ __device__ __forceinline__ void stitch_full(StitchLds &L, const JobDesc &j, int6
                 }
             }
         }
-        emit_line(L, j, oc, ol);
+        if (last_band) emit_line(L, j, oc, ol);
+        else *glb(j.cstate + col) = ol | (oc << 31);
     } else if (line < (int64_t)nb + n + nb - 1) {
         // Diagonal k: its pieces in the (strip, segment) blocks it crosses, in
         // order; a block's first and last black runs are folded across edges.
-        const int k = (int)(line - nb) - (n - 1);
+        const int dk = (int)(line - nb);                            // carry slot
+        const int k = dk - (n - 1);
         const int r0 = k < 0 ? -k : 0;                              // first row
         const int r1 = n - 1 < nb - 1 - k ? n - 1 : nb - 1 - k;     // last row
+        const int sa = r0 / H > s_lo ? r0 / H : s_lo;               // its strips in this band
+        const int sb = r1 / H < s_hi - 1 ? r1 / H : s_hi - 1;
+        if (sa > sb) return;
         const int W = j.seg_tiles * 64;                             // segment width
-        uint32_t open = 0;
-        for (int s = r0 / H; s <= r1 / H; ++s) {
+        uint32_t open = r0 / H < s_lo ? (uint32_t)*glb(j.dstate + dk) : 0u;
+        for (int s = sa; s <= sb; ++s) {
             const int ra = r0 > s * H ? r0 : s * H;
             const int rb = r1 < s * H + H - 1 ? r1 : s * H + H - 1;
             const int ca = ra + k, cb = rb + k;                     // its columns in strip s
@@ -1544,7 +1559,7 @@ __device__ __forceinline__ void stitch_full(StitchLds &L, const JobDesc &j, int6
                 const int hi = cb < g * W + W - 1 ? cb : g * W + W - 1;
                 const uint32_t len = (uint32_t)(hi - lo + 1);
                 const bool last = rb == r1 && hi == cb;
-                const int64_t idx = (int64_t)(s * j.segs + g) * j.dw + (s * H + H - 1 - g * W) + k;
+                const int64_t idx = (int64_t)((s - s_lo) * j.segs + g) * j.dw + (s * H + H - 1 - g * W) + k;
                 // A piece that begins where the diagonal begins, below the
                 // strip's top row, starts at the matrix's left border: nothing
                 // enters it, and its runs were counted where they ended.
@@ -1556,6 +1571,7 @@ __device__ __forceinline__ void stitch_full(StitchLds &L, const JobDesc &j, int6
                 open = last ? 0u : (uint32_t)*glb(j.dlast + idx);
             }
         }
+        if (r1 / H > sb) *glb(j.dstate + dk) = open;
     }
 }
 
@@ -2060,20 +2076,21 @@ Layout layout_of(const Job &jb) {
         // edge inside a strip).
         const int64_t nb = jb.n_cols;
         L.nstrips = (int)((n + L.H - 1) / L.H);
+        // Row bands as in auto mode: summaries for one band's strips.
+        L.band = jb.band_strips > 0 && jb.band_strips < L.nstrips ? jb.band_strips : L.nstrips;
+        L.nbands = (L.nstrips + L.band - 1) / L.band;
         const int T = (int)((nb - 1) / 64 + 1);
         const int min_tiles = std::max(8, L.H / 64);
-        int segs = (int)std::min<int64_t>((kFullItems + L.nstrips - 1) / L.nstrips,
+        int segs = (int)std::min<int64_t>((kFullItems + L.band - 1) / L.band,
                                           std::max(1, T / min_tiles));
         segs = std::max(segs, 1);
         L.seg_base = 0;
         L.seg_tiles = (T + segs - 1) / segs;
         L.segs = (T + L.seg_tiles - 1) / L.seg_tiles;
         L.dw = L.seg_tiles * 64 + L.H - 1;
-        L.ventries = (int64_t)L.nstrips * nb;
-        L.dentries = (int64_t)L.nstrips * L.segs * L.dw;
+        L.ventries = (int64_t)L.band * nb;
+        L.dentries = (int64_t)L.band * L.segs * L.dw;
         L.hentries = 0;
-        L.band = L.nstrips;
-        L.nbands = 1;
     }
     L.items = L.band * L.segs;
     if (L.ventries < 1) L.ventries = 1;
@@ -2096,11 +2113,13 @@ Layout layout_of(const Job &jb) {
     L.box_floats = (jb.mode != kModeMatrix && jb.kp.m <= kMaxM)
                        ? kBoxHeader + ((ncols - 1) / 64 + 1) * (int64_t)kBoxStride : 0;
     L.off_box = off; off += a256(sizeof(float) * (size_t)L.box_floats);
-    // Per-line carries between bands: the open run of each column of U and
-    // of each diagonal.
-    const size_t carries = L.nbands > 1 ? (size_t)n : 0;
-    L.off_cs = off; off += a256(sizeof(uint32_t) * carries);
-    L.off_ds = off; off += a256(sizeof(uint32_t) * carries);
+    // Per-line carries between bands: the open run of each column (of U in
+    // auto mode) and of each diagonal (n - 1 + nb of them in a full matrix).
+    const bool banded = L.nbands > 1;
+    const size_t ccarries = banded ? (size_t)(jb.mode == kModeAuto ? n : jb.n_cols) : 0;
+    const size_t dcarries = banded ? (size_t)(jb.mode == kModeAuto ? n : n + jb.n_cols - 1) : 0;
+    L.off_cs = off; off += a256(sizeof(uint32_t) * ccarries);
+    L.off_ds = off; off += a256(sizeof(uint32_t) * dcarries);
     L.bytes = off;
     return L;
 }
@@ -2201,7 +2220,7 @@ int stitch_blocks_of(const Job &jb) {
 size_t engine_job_scratch_bytes(const Job &job) { return layout_of(job).bytes; }
 
 int engine_band_strips(const Job &job, size_t limit) {
-    if (job.mode != kModeAuto || limit == 0) return 0;
+    if (limit == 0) return 0;
     Job jb = job;
     jb.band_strips = 0;
     const Layout all = layout_of(jb);
@@ -2360,7 +2379,8 @@ int engine_launch(const std::vector<Job> &jobs_in, void *launch_scratch, void *s
             const int lo = b * d.band_strips;
             const int hi = std::min(lo + d.band_strips, d.nstrips);
             const int items = (hi - lo) * d.segs;
-            const int64_t lines = 2 * ((int64_t)d.n - (int64_t)lo * d.H);
+            const int64_t lines = d.mode == kModeAuto ? 2 * ((int64_t)d.n - (int64_t)lo * d.H)
+                                                      : (int64_t)d.nb + d.n + d.nb - 1;
             hipLaunchKernelGGL(k_band, dim3(1), dim3(64), 0, st, ddesc, dgroups, dcounters, b);
             if (items > 0)
                 hipLaunchKernelGGL(kern, dim3(std::min(full_grid, items)), dim3(64 * jb.waves), lds, st,

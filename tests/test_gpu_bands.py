@@ -292,3 +292,80 @@ def test_non_finite_input_in_bands(cuda):
     for h in ("diag", "vert", "white"):
         assert np.array_equal(getattr(again, h), getattr(good_ref, h)), h
     comp.close()
+
+
+def _pack(R):
+    nr, nc = R.shape
+    words = (nc + 63) // 64
+    padded = np.zeros((nr, words * 64), dtype=np.uint64)
+    padded[:, :nc] = R
+    weights = np.uint64(1) << np.arange(64, dtype=np.uint64)
+    return (padded.reshape(nr, words, 64) * weights).sum(axis=2, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_cross_and_given_matrix_in_bands(case, cuda, oracle_lib):
+    """Full (not symmetric) matrices in row bands: cross recurrence of unequal
+    series (wide and tall, Theiler bands 0 and 3, long lines across band
+    edges) and given bit matrices, one strip per band and a few strips per
+    band, against the oracle."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    rng = np.random.default_rng(900 + case)
+    if case < 4:
+        na, nb = [(3000, 2100), (1500, 4100), (2600, 2600), (900, 3300)][case]
+        t = np.arange(max(na, nb) + 40)
+        base = np.sin(2 * np.pi * t / 311.0) + 0.03 * rng.normal(size=len(t))
+        a = base[:na].astype(np.float32)
+        b = base[17:17 + nb].astype(np.float32)
+        p = Params(m=2, tau=2, eps=0.12, norm=(2, 3, 1, 3)[case], theiler=(0, 3, 0, 3)[case])
+        ref = oracle_lib.cross_rqa(a, b, p)
+        run = lambda comp: comp.cross(torch.from_numpy(a).to(cuda), torch.from_numpy(b).to(cuda))
+    else:
+        nr, nc = (1900, 1300) if case == 4 else (700, 2500)
+        R = (rng.random((nr, nc)) < (0.2 if case == 4 else 0.6)).astype(np.uint64)
+        ii, jj = np.meshgrid(np.arange(nr), np.arange(nc), indexing="ij")
+        R[((ii // 150) + (jj // 170)) % 3 == 0] = 1        # long lines in every direction
+        bits = _pack(R)
+        p = Params(m=1, tau=1, eps=0.0, norm=3, theiler=(0, 2)[case - 4])
+        ref_h = oracle_lib.matrix_histograms(bits, nr, nc, p.theiler)
+        ref = (ref_h, oracle_lib.rect_measures(*ref_h, nr, nc, p.theiler, p.lmin, p.vmin, p.wmin))
+        dbits = torch.from_numpy(bits.view(np.int64)).to(cuda)
+        run = lambda comp: comp.matrix(dbits, nc)
+    comp = RQA.from_params(p)
+    comp.set_tiling(1 + case % 2, 0)
+    _announce("full one band", case=case)
+    whole, plan1 = run(comp), comp.last_plan()
+    assert plan1["bands"] == 1, plan1
+    assert_same(whole, *ref, tag=f"full case {case} one band")
+    for limit in (1, plan1["workspace_bytes"] // 3):
+        comp.set_workspace_limit(limit)
+        _announce("full bands", case=case, limit=limit)
+        res = run(comp)
+        plan = comp.last_plan()
+        assert plan["bands"] > 1, plan
+        assert_same(res, *ref, tag=f"full case {case} limit {limit} plan {plan}")
+    comp.close()
+
+
+def test_cross_full_size_in_bands(cuda):
+    """The 2 x 262,144-point Lorenz cross recurrence (1.1 GB of summaries in
+    one band) with 256 MiB, against the oracle's stored histograms."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    g = json.load(open(os.path.join(GOLDEN_DIR, "lorenz_cross_seed1_2.json")))
+    a, p = workload("lorenz", seed=g["seeds"][0], n=g["n_points"])
+    b, _ = workload("lorenz", seed=g["seeds"][1], n=g["n_points"])
+    comp = RQA.from_params(p)
+    comp.set_tiling(8, 0)
+    comp.set_workspace_limit(256 << 20)
+    _announce("cross full size 256 MiB")
+    res = comp.cross(torch.from_numpy(a).to(cuda), torch.from_numpy(b).to(cuda))
+    plan = comp.last_plan()
+    print(f"[plan] {plan}", flush=True)
+    comp.close()
+    assert plan["bands"] > 1 and plan["workspace_bytes"] <= 256 << 20, plan
+    hl = g["hist_len"]
+    for h in ("diag", "vert", "white"):
+        got, want = getattr(res, h), dense(g[h], hl - 1)
+        assert np.array_equal(got, want), f"cross {h} differs at {np.nonzero(got != want)[0][:8]}"
