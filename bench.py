@@ -200,15 +200,18 @@ def bench_headline(args, torch, RQA, workload):
     settle(comp, lambda: comp.run(ds), lambda: comp.result(histograms=False))
     log(f"[bench] lorenz N={len(s)} n_vec={n} eps={p.eps:.6g} waves={comp.last_launch()['waves']}; "
         f"warmup {args.warmup}")
+    # Host buffers for the histograms, reused across steps as a caller that
+    # loops would (fresh 8 MB arrays per step cost ~1.6 ms of page faults).
+    out_bufs = tuple(np.zeros(n + 1, dtype=np.uint64) for _ in range(3))
     for _ in range(args.warmup):
         comp.run(ds)
-        comp.result(histograms=True)
+        comp.result(histograms=True, out=out_bufs)
     tiles, stitch, prep = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         comp.run(ds)
-        res = comp.result(histograms=True)
+        res = comp.result(histograms=True, out=out_bufs)
         tm = comp.timings()
         tiles.append(tm["tiles_ms"])
         stitch.append(tm["stitch_ms"])
@@ -425,14 +428,15 @@ def bench_paper_e2(args, torch, RQA, workload):
         q = type(p)(m=p.m, tau=p.tau, eps=p.eps, norm=p.norm, lmin=2, vmin=2, wmin=2, theiler=w)
         comp = RQA.from_params(q)
         settle(comp, lambda: comp.run(ds), lambda: comp.result(histograms=False))
+        bufs = tuple(np.zeros(comp.hist_len(ds.numel()), dtype=np.uint64) for _ in range(3))
         comp.run(ds)
-        comp.result(histograms=True)
+        comp.result(histograms=True, out=bufs)
         t = []
         for _ in range(3):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             comp.run(ds)
-            r = comp.result(histograms=True)
+            r = comp.result(histograms=True, out=bufs)
             t.append(time.perf_counter() - t0)
         comp.close()
         sec = float(np.median(t))

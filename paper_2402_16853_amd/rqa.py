@@ -203,8 +203,14 @@ class RQA:
         self._hlen = [self.hist_len(s.numel())]
         return self
 
-    def result(self, histograms: bool = True) -> RQAResult:
-        return self._fetch(None, histograms)
+    def result(self, histograms: bool = True, out=None) -> RQAResult:
+        """Measures and (with ``histograms``) the three line-length histograms
+        of the last run.  ``out``: optional (diag, vert, white) host arrays of
+        uint64, C-contiguous, writeable and at least ``hist_len`` long, that
+        receive the histograms instead of new arrays (callers that loop reuse
+        their buffers; the result then holds views of their first hist_len
+        entries)."""
+        return self._fetch(None, histograms, out)
 
     def __call__(self, series, stream=None) -> RQAResult:
         self.run(series, stream)
@@ -287,8 +293,9 @@ class RQA:
         self.run_matrix(bits, n_cols, stream)
         return self.result()
 
-    def result_batch(self, index: int, histograms: bool = True) -> RQAResult:
-        return self._fetch(int(index), histograms)
+    def result_batch(self, index: int, histograms: bool = True, out=None) -> RQAResult:
+        """One window of the last batch; ``out`` as for :meth:`result`."""
+        return self._fetch(int(index), histograms, out)
 
     def results_batch(self):
         """Measures of every window of the last run in one library call: a numpy
@@ -307,13 +314,22 @@ class RQA:
             check(rc, "rqa_result_batch_all")
         return np.ctypeslib.as_array(out).copy(), status
 
-    def _fetch(self, index, histograms):
+    def _fetch(self, index, histograms, out=None):
         hl = self._hlen[0 if index is None else index] if self._hlen else 0
         ms = RqaMeasures()
         if histograms and hl > 1:
-            d = np.empty(hl, dtype=np.uint64)   # filled completely by the library
-            v = np.empty(hl, dtype=np.uint64)
-            w = np.empty(hl, dtype=np.uint64)
+            if out is None:
+                # filled completely by the library
+                d, v, w = (np.empty(hl, dtype=np.uint64) for _ in range(3))
+            else:
+                if len(out) != 3:
+                    raise ValueError("out must hold three arrays (diag, vert, white)")
+                for a in out:
+                    if (not isinstance(a, np.ndarray) or a.dtype != np.uint64 or a.ndim != 1
+                            or not a.flags.c_contiguous or not a.flags.writeable or a.size < hl):
+                        raise ValueError(f"each out array must be a writeable, C-contiguous 1-D "
+                                         f"uint64 array of at least {hl} entries")
+                d, v, w = (a[:hl] for a in out)
             ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in (d, v, w)]
         else:
             d = v = w = None

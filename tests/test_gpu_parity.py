@@ -197,3 +197,37 @@ def test_auto_column_segments(waves, cuda, oracle_lib):
             _announce("auto_segments", name=name, n=n, w=w, norm=norm, waves=waves)
             assert_same(run_gpu(s, q, cuda, waves=waves), *oracle_lib.rqa(s, q),
                         tag=f"{name} n={n} w={w} norm={norm} waves={waves}")
+
+
+def test_result_into_caller_buffers(cuda, oracle_lib):
+    """result(out=...) fills the caller's host arrays: the same histograms as new
+    arrays and as the oracle, entries past hist_len untouched, twice in a row
+    into the same buffers (the second run shorter, so its tails must be cleared),
+    and arrays of the wrong kind refused before the library is called."""
+    import torch
+    from paper_2402_16853_amd import RQA
+    s, p = workload("logistic", seed=3, n=2_600)
+    comp = RQA.from_params(p)
+    bufs = tuple(np.full(4_000, 7, dtype=np.uint64) for _ in range(3))
+    written = 0
+    for n in (2_600, 900):
+        x = np.ascontiguousarray(s[:n])
+        _announce("result_out", n=n)
+        comp.run(torch.from_numpy(x).to(cuda))
+        fresh = comp.result()
+        got = comp.result(out=bufs)
+        hl = len(fresh.diag)
+        written = max(written, hl)
+        ref = oracle_lib.rqa(x, p)
+        assert_same(got, *ref, tag=f"out n={n}")
+        for a, b, buf in zip((got.diag, got.vert, got.white), (fresh.diag, fresh.vert, fresh.white), bufs):
+            assert np.array_equal(a, b)
+            assert np.shares_memory(a, buf)
+            assert (buf[written:] == 7).all()
+    for bad in ((bufs[0], bufs[1]),
+                (bufs[0], bufs[1], np.zeros(4_000, dtype=np.int64)),
+                (bufs[0], bufs[1], np.zeros(10, dtype=np.uint64)),
+                (bufs[0], bufs[1], np.zeros(8_000, dtype=np.uint64)[::2])):
+        with pytest.raises(ValueError):
+            comp.result(out=bad)
+    comp.close()
