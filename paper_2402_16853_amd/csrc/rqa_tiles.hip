@@ -1872,6 +1872,7 @@ struct PlotDesc {
     int32_t n, nb, m, tau, theiler;
     float thr, thr0;
     int32_t row_tiles, col_tiles, chunks, cross;
+    int32_t xchunks;           // column chunks per XCD: ceil(chunks / 8)
     int32_t tail_len;
 };
 
@@ -1887,20 +1888,34 @@ __global__ void k_plot_tail(const PlotDesc d) {
 template <int NORM, int M>
 __global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
     const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
-    const int r = wv / d.chunks, q = wv - r * d.chunks;
-    if (r >= d.row_tiles) return;
+    // Workgroups go to the 8 XCDs in turn (block b to XCD b mod 8), each XCD
+    // with its own L2.  XCD x takes the column chunks q = x, x + 8, ... (a
+    // balanced share of the triangle), and its consecutive waves take
+    // consecutive row tiles of one chunk: the mirror tiles they write are then
+    // neighbouring words of the same rows, which meet in that XCD's L2.
+    const int x = (int)blockIdx.x & 7;
+    const int L = __builtin_amdgcn_readfirstlane((int)(blockIdx.x >> 3) * 4 + (int)(threadIdx.x >> 6));
+    const int qq = L / d.row_tiles, r = L - qq * d.row_tiles;
+    const int q = qq * 8 + x;
+    if (qq >= d.xchunks || q >= d.chunks) return;
     const int n = d.n, nb = d.nb, R = r * 64, i = R + lane;
     const int irow = i < n ? i : n - 1;
     const float *rowp = d.a + irow;
     float xr[M > 0 ? M : 1];
 #pragma unroll
     for (int k = 0; k < (M > 0 ? M : 1); ++k) xr[k] = M > 0 ? glb(rowp)[(int64_t)k * d.tau] : 0.0f;
-    int cbeg = q * kPlotChunk;
+    const int cq = q * kPlotChunk;
+    int cbeg = cq;
     const int cend = cbeg + kPlotChunk < d.col_tiles ? cbeg + kPlotChunk : d.col_tiles;
     if (!d.cross && cbeg < r) cbeg = r;
     const int64_t band = d.theiler;
-    for (int c = cbeg; c < cend; ++c) {
+    // A whole chunk: this lane's row words are written together at its end.
+    const bool whole = cbeg == cq && cend - cq == kPlotChunk;
+    uint64_t rowbuf[kPlotChunk];
+#pragma unroll
+    for (int u = 0; u < kPlotChunk; ++u) {
+        const int c = cq + u;
+        if (c < cbeg || c >= cend) continue;
         const int jbase = c * 64;
         const ConstF cols = to_const(c == d.col_tiles - 1 ? d.tail : d.b + jbase);
         uint32_t xlo, xhi;
@@ -1917,13 +1932,19 @@ __global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
             }
         }
         const uint64_t X = mk64(xlo, xhi) & vm;
-        if (i < n) d.bits[(int64_t)i * d.words + c] = X;
+        if (whole) rowbuf[u] = X;
+        else if (i < n) d.bits[(int64_t)i * d.words + c] = X;
         if (!d.cross && c > r) {
             uint32_t lo = (uint32_t)X, hi = (uint32_t)(X >> 32);
             transpose64(lo, hi, lane);
             const int jr = jbase + lane;   // row of the mirror tile
             if (jr < n) d.bits[(int64_t)jr * d.words + r] = mk64(lo, hi);
         }
+    }
+    if (whole && i < n) {
+        uint64_t *dst = d.bits + (int64_t)i * d.words + cq;
+#pragma unroll
+        for (int u = 0; u < kPlotChunk; ++u) dst[u] = rowbuf[u];
     }
 }
 
@@ -2511,14 +2532,15 @@ int engine_plot(const KParams &kp, const float *a, int64_t na_points, const floa
     pd.row_tiles = (int32_t)((n + 63) / 64);
     pd.col_tiles = (int32_t)((nb + 63) / 64);
     pd.chunks = (pd.col_tiles + kPlotChunk - 1) / kPlotChunk;
+    pd.xchunks = (pd.chunks + 7) / 8;
     pd.cross = cross ? 1 : 0;
     pd.tail_len = (int32_t)engine_plot_tail_floats(kp);
     hipLaunchKernelGGL(k_plot_tail, dim3((pd.tail_len + 255) / 256), dim3(256), 0, st, pd);
     PlotKernel kern = kp.norm == RQA_NORM_L1 ? pick_plot<RQA_NORM_L1>(kp.m)
                       : kp.norm == RQA_NORM_L2 ? pick_plot<RQA_NORM_L2>(kp.m)
                                                : pick_plot<RQA_NORM_LINF>(kp.m);
-    const int64_t waves = (int64_t)pd.row_tiles * pd.chunks;
-    hipLaunchKernelGGL(kern, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, pd);
+    const int64_t xwaves = (int64_t)pd.row_tiles * pd.xchunks;   // waves per XCD
+    hipLaunchKernelGGL(kern, dim3((unsigned)(8 * ((xwaves + 3) / 4))), dim3(256), 0, st, pd);
     return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
 }
 
