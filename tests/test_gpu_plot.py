@@ -105,3 +105,25 @@ def test_plot_and_matrix_at_benchmark_size(cuda, oracle_lib):
     for k, ref in meas.items():
         got = via.measures[k]
         assert (np.isnan(ref) and np.isnan(got)) or abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), k
+
+
+@pytest.mark.parametrize("na,nb", [(8_193, None), (9_253, None), (3_000, 20_000), (20_000, 3_000)])
+def test_plot_chunk_layouts(na, nb, cuda, oracle_lib):
+    """Plots whose 16-tile column chunks do not divide evenly over the 8 XCD
+    groups of the wave-to-tile map (9, 10 and 20 chunks; more or fewer row
+    tiles than column tiles), against the oracle bit for bit."""
+    from paper_2402_16853_amd import RQA
+    rng = np.random.default_rng(na + (nb or 0))
+    p = Params(m=3, tau=2, eps=0.3, norm=3, theiler=1)
+    a = (np.cumsum(rng.normal(size=na)) * 0.1).astype(np.float32)
+    comp = RQA.from_params(p)
+    if nb is None:
+        _announce("plot_layout", n=na)
+        got = comp.plot(dev(a, cuda)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, oracle_lib.plot(a, p)), "auto plot"
+    else:
+        b = (np.cumsum(rng.normal(size=nb)) * 0.1).astype(np.float32)
+        _announce("plot_layout_cross", na=na, nb=nb)
+        got = comp.plot(dev(a, cuda), dev(b, cuda)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, oracle_lib.plot(a, p, b)), "cross plot"
+    comp.close()
