@@ -647,7 +647,7 @@ int plot(rqa_handle *h, const float *a, int64_t na_points, const float *b, int64
     if (na > (int64_t(1) << 31) - 2 || nb > (int64_t(1) << 31) - 2) return RQA_EINVAL;
     if (words < (nb + 63) / 64) return RQA_ESIZE;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    const size_t need = sizeof(float) * static_cast<size_t>(engine_plot_tail_floats(kp));
+    const size_t need = sizeof(float) * static_cast<size_t>(engine_plot_scratch_floats(kp, nb));
     if (!h->plot_done && hipEventCreateWithFlags(&h->plot_done, hipEventDisableTiming) != hipSuccess)
         return RQA_EDEVICE;
     if (h->plot_tail_bytes < need) {

@@ -155,10 +155,13 @@ int engine_launch_static(Job jb, void *scratch, hipStream_t stream);
 
 // Recurrence plot: the masked matrix of series a (b == nullptr) or the cross
 // matrix of a and b, bit-packed into `bits` (rows of `words` u64), on `stream`.
-// `tail` holds engine_plot_tail_floats(kp) device floats of scratch.
-int64_t engine_plot_tail_floats(const KParams &kp);
+// `scratch` holds engine_plot_scratch_floats(kp, nb) device floats (the last
+// column tile's coordinates and the column boxes of the exact tile pruning),
+// nb being the number of column vectors.
+int64_t engine_plot_scratch_floats(const KParams &kp, int64_t nb);
 int engine_plot(const KParams &kp, const float *a, int64_t na_points, const float *b,
-                int64_t nb_points, uint64_t *bits, int64_t words, float *tail, hipStream_t stream);
+                int64_t nb_points, uint64_t *bits, int64_t words, float *scratch,
+                hipStream_t stream);
 
 // Host FP64 measures from histograms of length n+1.
 void measures_from_hist(const uint64_t *diag, const uint64_t *vert, const uint64_t *white,

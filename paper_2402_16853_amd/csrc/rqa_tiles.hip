@@ -1873,10 +1873,37 @@ struct PlotDesc {
     float thr, thr0;
     int32_t row_tiles, col_tiles, chunks, cross;
     int32_t xchunks;           // column chunks per XCD: ceil(chunks / 8)
+    float *box;                // per column tile kBoxStride floats: (lo_k, hi_k), k < kBoxK
     int32_t tail_len;
 };
 
 constexpr int kPlotChunk = 16;   // column tiles per wave
+
+// Column boxes of the plot's column tiles (the records k_box_bounds writes for
+// a job, for the plot's columns; always used: the test costs one scalar load
+// and a few compares per tile).
+__global__ void k_plot_boxes(const PlotDesc d) {
+    const int K = d.m < kBoxK ? d.m : kBoxK;
+    const int64_t total = (int64_t)d.col_tiles * K;
+    const float bnd = d.thr0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(t % K);
+        const int64_t c = t / K;
+        const int64_t j0 = c * 64;
+        const int64_t j1 = j0 + 64 < d.nb ? j0 + 64 : d.nb;
+        float cmin = INFINITY, cmax = -INFINITY;
+        const float *col = d.b + (int64_t)k * d.tau;
+        for (int64_t q = j0; q < j1; ++q) {
+            const float v = col[q];
+            cmin = fminf(cmin, v);
+            cmax = fmaxf(cmax, v);
+        }
+        float *rec = d.box + c * kBoxStride;
+        rec[2 * k] = box_lo(cmin, bnd);
+        rec[2 * k + 1] = box_hi(cmax, bnd);
+    }
+}
 
 __global__ void k_plot_tail(const PlotDesc d) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1919,7 +1946,11 @@ __global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
         const int jbase = c * 64;
         const ConstF cols = to_const(c == d.col_tiles - 1 ? d.tail : d.b + jbase);
         uint32_t xlo, xhi;
-        tile_bits<NORM, M, true>(cols, d.tau, xr, rowp, d.m, d.thr, d.thr0, nullptr, xlo, xhi);
+        // The predicate path of the tile kernel: a tile that its column box
+        // rules out for every row is empty without evaluating a pair.
+        tile_bits<NORM, M, false>(cols, d.tau, xr, rowp, d.m, d.thr, d.thr0,
+                                  M > 0 ? to_const(d.box) + (int64_t)c * kBoxStride : nullptr, xlo,
+                                  xhi);
         uint64_t vm = 0ull;
         if (i < n) {
             const int hv = nb - jbase < 64 ? nb - jbase : 64;
@@ -2508,17 +2539,24 @@ int engine_launch_static(Job jb, void *scratch, hipStream_t st) {
     return hipGetLastError() == hipSuccess ? RQA_OK : RQA_EDEVICE;
 }
 
-int64_t engine_plot_tail_floats(const KParams &kp) { return 64 + (int64_t)(kp.m - 1) * kp.tau; }
+// The last column tile's coordinates, then (32-byte aligned) the column boxes.
+static int64_t plot_tail_floats(const KParams &kp) {
+    return (64 + (int64_t)(kp.m - 1) * kp.tau + 7) / 8 * 8;
+}
+int64_t engine_plot_scratch_floats(const KParams &kp, int64_t nb) {
+    return plot_tail_floats(kp) + (nb + 63) / 64 * kBoxStride;
+}
 
 int engine_plot(const KParams &kp, const float *a, int64_t na_points, const float *b,
-                int64_t nb_points, uint64_t *bits, int64_t words, float *tail, hipStream_t st) {
+                int64_t nb_points, uint64_t *bits, int64_t words, float *scratch, hipStream_t st) {
     const int64_t d = (int64_t)(kp.m - 1) * kp.tau;
     const bool cross = b != nullptr;
     const int64_t n = na_points - d, nb = cross ? nb_points - d : n;
     PlotDesc pd{};
     pd.a = a;
     pd.b = cross ? b : a;
-    pd.tail = tail;
+    pd.tail = scratch;
+    pd.box = scratch + plot_tail_floats(kp);
     pd.bits = bits;
     pd.words = words;
     pd.nb_points = cross ? nb_points : na_points;
@@ -2534,8 +2572,13 @@ int engine_plot(const KParams &kp, const float *a, int64_t na_points, const floa
     pd.chunks = (pd.col_tiles + kPlotChunk - 1) / kPlotChunk;
     pd.xchunks = (pd.chunks + 7) / 8;
     pd.cross = cross ? 1 : 0;
-    pd.tail_len = (int32_t)engine_plot_tail_floats(kp);
+    pd.tail_len = (int32_t)(64 + (int64_t)(kp.m - 1) * kp.tau);
     hipLaunchKernelGGL(k_plot_tail, dim3((pd.tail_len + 255) / 256), dim3(256), 0, st, pd);
+    if (kp.m > 0) {
+        const int64_t box_threads = (int64_t)pd.col_tiles * std::min(kp.m, kBoxK);
+        const int box_grid = (int)std::min<int64_t>((box_threads + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_plot_boxes, dim3(box_grid), dim3(256), 0, st, pd);
+    }
     PlotKernel kern = kp.norm == RQA_NORM_L1 ? pick_plot<RQA_NORM_L1>(kp.m)
                       : kp.norm == RQA_NORM_L2 ? pick_plot<RQA_NORM_L2>(kp.m)
                                                : pick_plot<RQA_NORM_LINF>(kp.m);
