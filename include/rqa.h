@@ -160,7 +160,11 @@ int rqa_run_matrix(rqa_handle *h, const uint64_t *d_bits, int64_t n_rows, int64_
  * 0 and words past ceil(n/64) are left unchanged.  n*words_per_row*8 bytes
  * (125 MB at n = 100,000): meant for small series and windows.  The output can
  * be fed back to rqa_run_matrix.  Asynchronous on hip_stream; the caller keeps
- * d_series and d_bits alive until the stream has passed the call.
+ * d_series and d_bits alive until the stream has passed the call.  The handle
+ * keeps a device scratch buffer for the plot (the last column tile's
+ * coordinates and one 32-byte record per 64 columns); a plot with more
+ * columns than any before on this handle grows it (hipMalloc, after the
+ * previous plot has passed), RQA_ENOMEM if that fails.
  * RQA_ESIZE if words_per_row is too small, RQA_ETOOSHORT as rqa_run. */
 int rqa_plot(rqa_handle *h, const float *d_series, int64_t n_points, uint64_t *d_bits,
              int64_t words_per_row, void *hip_stream);
