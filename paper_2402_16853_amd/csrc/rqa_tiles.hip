@@ -518,11 +518,11 @@ __device__ __forceinline__ bool box_decides(ConstF rec, const float *xr) {
 //    of undecided tiles, against 24% for the first-coordinate test), but its
 //    record took SGPRs the kernel did not have (spills) and measured slower
 //    than evaluating the chunk;
-//  * D0 (the recurrence plot, and m >= 5): each chunk first takes the first
+//  * m >= 5 (the first-coordinate test): each chunk first takes the first
 //    coordinate's differences; when no lane of the wave has |d_0| <= thr0 in
 //    the chunk, all 8 x 64 pairs are non-recurrent and the other coordinates
 //    are not evaluated.
-template <int NORM, int M, bool D0>
+template <int NORM, int M>
 __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
                                           const float *__restrict__ rowp, int m, float thr_s,
                                           float thr0_s, ConstF box, uint32_t &lo, uint32_t &hi) {
@@ -552,7 +552,7 @@ __device__ __forceinline__ void tile_bits(ConstF cols, int tau, const float *xr,
                 // test the compiler rebuilt their addresses with long chains
                 // of 64-bit scalar adds (measured 29% slower on the L1, m = 5
                 // windows).
-                if (D0 || M >= 5) {
+                if (M >= 5) {
                     // All of the chunk's coordinates are loaded up front (the
                     // empty asm keeps the compiler from sinking the loads of
                     // the other coordinates into the branch, which would add a
@@ -949,7 +949,7 @@ __device__ void process_strip(const JobDesc &j, int item, StripLds &L) {
                 xhi = (uint32_t)(word >> 32);
             } else {
                 const ConstF cols = to_const((c == j.c_last) ? j.tail : j.sb + jbase);
-                tile_bits<NORM, M, false>(cols, tau, xr, rowp, j.m, j.thr, j.thr0,
+                tile_bits<NORM, M>(cols, tau, xr, rowp, j.m, j.thr, j.thr0,
                                           box == nullptr ? nullptr : box + (int64_t)c * kBoxStride,
                                           xlo, xhi);
             }
@@ -1948,7 +1948,7 @@ __global__ void __launch_bounds__(256) k_plot(const PlotDesc d) {
         uint32_t xlo, xhi;
         // The predicate path of the tile kernel: a tile that its column box
         // rules out for every row is empty without evaluating a pair.
-        tile_bits<NORM, M, false>(cols, d.tau, xr, rowp, d.m, d.thr, d.thr0,
+        tile_bits<NORM, M>(cols, d.tau, xr, rowp, d.m, d.thr, d.thr0,
                                   M > 0 ? to_const(d.box) + (int64_t)c * kBoxStride : nullptr, xlo,
                                   xhi);
         uint64_t vm = 0ull;
