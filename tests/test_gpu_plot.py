@@ -127,3 +127,19 @@ def test_plot_chunk_layouts(na, nb, cuda, oracle_lib):
         got = comp.plot(dev(a, cuda), dev(b, cuda)).cpu().numpy().view(np.uint64)
         assert np.array_equal(got, oracle_lib.plot(a, p, b)), "cross plot"
     comp.close()
+
+
+def test_plot_scratch_grows_and_is_reused(cuda, oracle_lib):
+    """One handle, plots of 300, 5,000 and again 300 points (the handle's plot
+    scratch, which holds the column boxes, grows for the second and is reused
+    for the third): every plot equals the oracle's."""
+    from paper_2402_16853_amd import RQA
+    rng = np.random.default_rng(77)
+    p = Params(m=2, tau=3, eps=0.25, norm=2, theiler=1)
+    comp = RQA.from_params(p)
+    for k, n in enumerate((300, 5_000, 300)):
+        a = (np.cumsum(rng.normal(size=n)) * 0.1).astype(np.float32)
+        _announce("plot_scratch", call=k, n=n)
+        got = comp.plot(dev(a, cuda)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, oracle_lib.plot(a, p)), f"plot {k} (n={n})"
+    comp.close()
